@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Throughput of the lazy-PCA denoising job on one MI355X.
+
+A step is one whole job on a synthetic 2048x2048 image with L = 256 grey levels, 16
+independent chains and 1000 sweeps (truncated-linear prior T = 32, J = 0.05, q = 1.0,
+sigma = 20 levels): initialisation from the observation, every sweep with its running
+mean and histogram, and the posterior-mean and marginal-mode readouts.  The observation
+is resident in HBM before the timed region.  Prints one JSON line.
+
+Roofline: the sweep kernel is bound by vector ALU work; `roofline` reports its
+algorithmic VALU lane-operations per launch divided by its average launch time (HIP
+events on the launch stream) against the MI355X VALU issue rate.  `cpu_baseline` is
+the CPU reference timed on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit op per lane per clock
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_14869_amd", "csrc", "pca_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c3_traffic.txt")
+
+
+def valu_ops_per_site_update(levels: int, chains: int) -> float:
+    """Algorithmic VALU lane-ops per site update: per (chain, level) three byte-SADs, the
+    two-op table index and one fma; per (pixel, level) the 15-op data factor shared by
+    the chains of the pixel."""
+    return levels * (6.0 + 15.0 / chains)
+
+
+def hbm_bytes_per_sweep(N: int, chains: int, tally: bool) -> float:
+    """State read and write, observation read, uint32 sum read-modify-write, and (tally
+    sweeps) one uint16 counter read-modify-write per chain."""
+    b = 2.0 * chains * N + 4.0 * N + 8.0 * N
+    if tally:
+        b += 4.0 * chains * N
+    return b
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_units: float):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; otherwise None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(wl, seconds: float):
+    """The oracle on sampled site updates of sweep 0 of the same workload, single thread."""
+    import numpy as np
+    import oracle
+    p = oracle.Params(**wl.params())
+    x0 = oracle.init_state(p, wl.obs)
+    rng = np.random.default_rng(7)
+    N = wl.height * wl.width
+    done = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        n = 4096
+        ch = rng.integers(0, wl.chains, n).astype(np.int32)
+        px = rng.integers(0, N, n).astype(np.int64)
+        oracle.update_sites(p, wl.obs, x0, 0, ch, px)
+        done += n
+    dt = time.perf_counter() - t0
+    return {"value": done / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{done} random (chain, pixel) site updates of sweep 0 of the same 2048x2048 L=256 "
+                      f"workload, {dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--sweeps", type=int, default=None, help="override the workload's sweep count")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the sampler has no multi-GPU path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_14869_amd import Sampler
+    from workloads import synth
+
+    wl = synth.make_workload(args.workload, sweeps=args.sweeps)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    obs = torch.from_numpy(wl.obs).to(dev)
+    kw = wl.params()
+    kw.pop("height")
+    kw.pop("width")
+    levels = kw.pop("levels")
+    stream = torch.cuda.current_stream()
+    N = wl.height * wl.width
+
+    def job(timing):
+        s = Sampler(obs, levels=levels, **kw)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(stream)
+        s.sweep(wl.sweeps)
+        ev1.record(stream)
+        mean = s.posterior_mean()
+        mpm = s.marginal_map() if wl.tally_stride > 0 else None
+        timing.append((ev0, ev1))
+        return s, mean, mpm
+
+    for _ in range(args.warmup):
+        s, _, _ = job([])
+        s.sync()
+        s.close()
+    torch.cuda.synchronize()
+
+    timing = []
+    samplers = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s, mean, mpm = job(timing)
+        samplers.append(s)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for s in samplers:
+        s.sync()
+        s.close()
+
+    sweep_ms = [a.elapsed_time(b) for a, b in timing]
+    avg_launch_s = (sum(sweep_ms) / len(sweep_ms)) / 1e3 / wl.sweeps
+    su_total = wl.site_updates * args.steps
+    value = su_total / elapsed
+
+    ops_per_su = valu_ops_per_site_update(wl.levels, wl.chains)
+    launch_ops = ops_per_su * N * wl.chains
+    achieved = launch_ops / avg_launch_s / 1e12
+    traffic = measured_traffic(N * wl.chains)
+    hbm_alg = hbm_bytes_per_sweep(N, wl.chains, wl.tally_stride > 0)
+    out = {
+        "metric": "site-updates/s",
+        "value": value,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{wl.name}: {wl.height}x{wl.width} image, L={wl.levels}, {wl.chains} chains, "
+                        f"{wl.sweeps} sweeps, truncated-linear prior T={wl.trunc} J={wl.J} q={wl.q}, "
+                        f"sigma={wl.sigma} levels, 4-neighbour, mean + marginal mode",
+            "height": wl.height, "width": wl.width, "levels": wl.levels, "chains": wl.chains,
+            "sweeps": wl.sweeps, "site_updates_per_step": wl.site_updates,
+        },
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_VALU_TOPS,
+            "unit": "TOP/s",
+            "frac": achieved / PEAK_VALU_TOPS,
+            "traffic": traffic,
+            "kernel": "sweep_kernel",
+            "ops_per_site_update": ops_per_su,
+            "avg_launch_ms": avg_launch_s * 1e3,
+        },
+        "hbm": {
+            "algorithmic_bytes_per_launch": hbm_alg,
+            "achieved_GBs": hbm_alg / avg_launch_s / 1e9,
+            "peak_GBs": PEAK_HBM_GBS,
+            "frac": hbm_alg / avg_launch_s / 1e9 / PEAK_HBM_GBS,
+        },
+        "level_evaluations_per_s": value * wl.levels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,129 @@
+/*
+ * pca.h - C ABI of the lazy Probabilistic Cellular Automaton (PCA) sampler for lattice
+ * MRF posteriors, built for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Costarelli, Piconi, Troiani, "Bayesian Inversion via Probabilistic Cellular
+ * Automata: an application to image denoising" (arXiv 2507.14869).  Every sweep draws
+ * the new grey level of every pixel of every chain independently from the lazy
+ * posterior conditional of Sec. 5.2 (pair Hamiltonian eq.
+ * (denoising_pair_posterior_Hamiltonian)): a nearest-neighbour pair prior with coupling
+ * J, an inertia weight q tying each site to its own previous value, and a Gaussian data
+ * term with standard deviation sigma that the inverse temperature beta does not scale
+ * (Sec. 2 eq. (posterior_hamiltonian)).  The sweep also accumulates the running
+ * posterior mean (Sec. 2 'Bayesian inference', law-of-large-numbers average) and a
+ * per-pixel level histogram for the marginal posterior mode.
+ *
+ * Conventions shared by all entry points:
+ *  - Every device pointer is caller-owned and must stay valid until the work enqueued
+ *    on `stream` that uses it has finished.  Pointers are plain device addresses (for
+ *    example a torch tensor's data_ptr()).
+ *  - `stream` is a hipStream_t passed as void*; NULL is the default stream.  All calls
+ *    except pca_sync and pca_destroy only enqueue work and return immediately.
+ *  - Argument errors are returned synchronously as negative codes and leave the context
+ *    unchanged.  Errors raised by the device are returned by the next call on the
+ *    context or by pca_sync.  pca_last_error() gives a message for the calling thread.
+ *  - A context belongs to the device that was current at pca_init; call it with that
+ *    device current.  A context is not thread-safe; distinct contexts are independent.
+ *  - Randomness depends only on (seed, chain, sweep index, pixel): results do not depend
+ *    on how sweeps are split across calls, on streams, or on other work on the device.
+ *  - Layouts: images are row-major [height][width]; chain states are uint8 level
+ *    indices, row-major [chains][height][width] at this boundary.
+ */
+#ifndef PCA_MI355X_H
+#define PCA_MI355X_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pca_ctx pca_ctx; /* opaque, library-owned */
+
+enum {
+    PCA_OK = 0,
+    PCA_EINVAL = -1,  /* invalid argument or parameter */
+    PCA_ENOMEM = -2,  /* device allocation failed */
+    PCA_EDEVICE = -3, /* HIP runtime or kernel error */
+    PCA_ESTATE = -4   /* operation not valid in the context's current state */
+};
+
+enum {
+    PCA_PRIOR_POTTS = 0,       /* Potts pair potential V = -J if equal else +J, eq. (prior_pair_potential) */
+    PCA_PRIOR_TRUNC_LINEAR = 1 /* J * min(|a - b|, trunc) in level units */
+};
+
+typedef struct {
+    int32_t height, width; /* lattice size, >= 1 each, height*width < 2^31 */
+    int32_t levels;        /* L grey levels, 2..256; level k has value vmin + k*(vmax-vmin)/(L-1) (Sec. 4) */
+    int32_t chains;        /* independent chains, 1..1024 */
+    int32_t neighbourhood; /* 4 or 8; the paper's neighbourhood eq. (neighborhood) is 8; free boundary */
+    int32_t prior;         /* PCA_PRIOR_* */
+    int32_t trunc;         /* truncation T >= 1 of the linear prior (ignored for Potts) */
+    float J;               /* pair coupling >= 0 */
+    float q;               /* inertia >= 0: log-odds penalty beta*q for a changed site (L0 norm, Sec. 5.2) */
+    float sigma;           /* noise standard deviation > 0, value units */
+    float vmin, vmax;      /* values of levels 0 and L-1, vmax > vmin */
+    const float *beta;     /* host array of per-sweep inverse temperatures (> 0), copied at init; NULL => 1 */
+    int32_t beta_len;      /* sweeps past the end reuse the last value (schedule of Sec. 6) */
+    uint64_t seed;         /* Philox4x32-10 key */
+    int32_t init_mode;     /* 0: every chain starts at the level nearest the observation; 1: uniform random */
+    int32_t burn_in;       /* sweeps with index < burn_in are not accumulated */
+    int32_t tally_stride;  /* histogram every tally_stride-th sweep from burn_in on; 0 = no histogram */
+} pca_params;
+
+/* Creates a context: validates `params`, allocates the chain states, the mean
+ * accumulator and (if tally_stride > 0) the histogram of height*width*levels uint16
+ * counters, converts the observation to level units and initialises every chain.
+ * obs_dev: device float32 [height][width] observation in value units, finite; it is read
+ * during the enqueued initialisation only.  On success *out receives the context and the
+ * sweep index is 0.  Errors: PCA_EINVAL (bad parameters, NULL pointers), PCA_ENOMEM,
+ * PCA_EDEVICE. */
+int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_ctx **out);
+
+/* Enqueues n >= 0 sweeps of the lazy PCA (Sec. 5.2): sweep t reads state t of every chain
+ * and writes state t+1, drawing each site from its conditional given the previous state
+ * only; then adds every chain's new levels to the mean accumulator if t >= burn_in and to
+ * the histogram on tally sweeps.  n = 0 is a no-op.  Errors: PCA_EINVAL (n < 0),
+ * PCA_ESTATE (the uint32 sum or a uint16 histogram counter could overflow), PCA_EDEVICE. */
+int pca_sweep(pca_ctx *ctx, int32_t n, void *stream);
+
+/* Writes the posterior-mean estimate (Sec. 2, conditional mean; Monte Carlo average over
+ * chains and accumulated sweeps) in value units: out = vmin + (sum/count)*(vmax-vmin)/(L-1),
+ * computed in double and rounded once.  out_dev: device float32 [height][width].
+ * Errors: PCA_ESTATE if no sweep has been accumulated yet, PCA_EINVAL. */
+int pca_posterior_mean(pca_ctx *ctx, float *out_dev, void *stream);
+
+/* Writes the marginal posterior mode: per pixel the level index with the largest tally,
+ * ties to the lowest level.  out_dev: device uint8 [height][width].  Errors: PCA_ESTATE if
+ * the histogram is disabled or empty, PCA_EINVAL. */
+int pca_marginal_map(pca_ctx *ctx, uint8_t *out_dev, void *stream);
+
+/* Copies the current states (the last sample of each chain, the paper's MAP output after
+ * annealing, Sec. 6) to out_dev: device uint8 [chains][height][width]. */
+int pca_get_state(pca_ctx *ctx, uint8_t *out_dev, void *stream);
+
+/* Replaces the current states with in_dev (device uint8 [chains][height][width], every
+ * value < levels; larger values are clamped to levels-1) and sets the sweep index to t >= 0.
+ * Accumulators are kept.  Used to resume a run or to re-synchronise with another
+ * implementation.  Errors: PCA_EINVAL. */
+int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream);
+
+/* Reports the sweep index, the number of samples in the mean accumulator (chains times
+ * accumulated sweeps) and the number of tally sweeps.  Any pointer may be NULL. */
+int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *tallies);
+
+/* Waits for all work the context enqueued and reports any device error. */
+int pca_sync(pca_ctx *ctx);
+
+/* Waits for the context's last stream, then frees it.  NULL is a no-op. */
+int pca_destroy(pca_ctx *ctx);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *pca_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,100 @@
+"""Lazy Probabilistic Cellular Automaton sampler for lattice-MRF image denoising on
+AMD Instinct MI355X (gfx950), after Costarelli, Piconi, Troiani (arXiv 2507.14869).
+
+The sampler is the HIP library ``libpca.so`` behind the C ABI of ``include/pca.h``;
+``_lib`` binds its entry points under the same names and :class:`Sampler` holds a
+context together with the torch tensors that carry device memory and streams.
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+from . import _lib
+from ._lib import (PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_params, pca_destroy, pca_get_state,  # noqa
+                   pca_init, pca_last_error, pca_marginal_map, pca_posterior_mean, pca_set_state, pca_stats,
+                   pca_sweep, pca_sync)
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream)
+
+
+class Sampler:
+    """One lazy-PCA run on the current GPU: ``obs`` is a float32 [H, W] tensor in value units.
+
+    Keyword parameters are those of ``pca_params`` (include/pca.h).  All calls enqueue on
+    ``stream`` (default: torch's current stream) and return torch tensors.
+    """
+
+    def __init__(self, obs, *, levels: int, chains: int = 1, neighbourhood: int = 4,
+                 prior: int = PCA_PRIOR_TRUNC_LINEAR, trunc: int = 1, J: float = 0.0, q: float = 0.0,
+                 sigma: float = 1.0, vmin: float = 0.0, vmax: Optional[float] = None,
+                 beta: Sequence[float] = (), seed: int = 0, init_mode: int = 0, burn_in: int = 0,
+                 tally_stride: int = 0, stream=None):
+        import torch
+        _lib.load()
+        if obs.dtype != torch.float32 or obs.dim() != 2 or not obs.is_cuda:
+            raise ValueError("obs must be a float32 [H, W] CUDA tensor")
+        self.obs = obs.contiguous()
+        self.height, self.width = int(obs.shape[0]), int(obs.shape[1])
+        self.levels, self.chains = levels, chains
+        self.device = obs.device
+        self.params, self._beta_buf = make_params(
+            height=self.height, width=self.width, levels=levels, chains=chains, neighbourhood=neighbourhood,
+            prior=prior, trunc=trunc, J=J, q=q, sigma=sigma, vmin=vmin, vmax=vmax, beta=beta, seed=seed,
+            init_mode=init_mode, burn_in=burn_in, tally_stride=tally_stride)
+        self.ctx = pca_init(self.params, self.obs.data_ptr(), _stream_handle(stream))
+
+    def sweep(self, n: int = 1, stream=None) -> "Sampler":
+        pca_sweep(self.ctx, n, _stream_handle(stream))
+        return self
+
+    def posterior_mean(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.height, self.width), dtype=torch.float32, device=self.device)
+        pca_posterior_mean(self.ctx, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def marginal_map(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.height, self.width), dtype=torch.uint8, device=self.device)
+        pca_marginal_map(self.ctx, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def state(self, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.chains, self.height, self.width), dtype=torch.uint8, device=self.device)
+        pca_get_state(self.ctx, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def set_state(self, x, t: int, stream=None) -> "Sampler":
+        import torch
+        if x.dtype != torch.uint8 or tuple(x.shape) != (self.chains, self.height, self.width) or not x.is_cuda:
+            raise ValueError("state must be a uint8 [chains, H, W] CUDA tensor")
+        self._set_buf = x.contiguous()
+        pca_set_state(self.ctx, self._set_buf.data_ptr(), t, _stream_handle(stream))
+        return self
+
+    def stats(self):
+        """(sweep index, samples in the mean, tally sweeps)."""
+        return pca_stats(self.ctx)
+
+    def sync(self):
+        pca_sync(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            pca_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,140 @@
+"""ctypes binding of libpca.so: the C-ABI entry points of include/pca.h, same names.
+
+Argument marshalling only.  Device memory and streams come from torch; every step of
+the sampler runs in the library's HIP kernels.  Importing this module does not touch
+the GPU; loading fails loudly if the built library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpca.so")
+
+PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE = 0, -1, -2, -3, -4
+PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR = 0, 1
+
+EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "pca_get_state", "pca_set_state",
+            "pca_stats", "pca_sync", "pca_destroy", "pca_last_error")
+
+
+class PcaError(RuntimeError):
+    def __init__(self, code: int, what: str, msg: str):
+        super().__init__(f"{what} failed ({code}): {msg}")
+        self.code = code
+
+
+class pca_params(ctypes.Structure):
+    _fields_ = [
+        ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("levels", ctypes.c_int32),
+        ("chains", ctypes.c_int32), ("neighbourhood", ctypes.c_int32), ("prior", ctypes.c_int32),
+        ("trunc", ctypes.c_int32),
+        ("J", ctypes.c_float), ("q", ctypes.c_float), ("sigma", ctypes.c_float),
+        ("vmin", ctypes.c_float), ("vmax", ctypes.c_float),
+        ("beta", ctypes.POINTER(ctypes.c_float)), ("beta_len", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("init_mode", ctypes.c_int32), ("burn_in", ctypes.c_int32), ("tally_stride", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """The loaded libpca.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(there is no fallback implementation)")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        pp = ctypes.POINTER(pca_params)
+        lib.pca_init.argtypes = [pp, vp, vp, ctypes.POINTER(vp)]
+        lib.pca_sweep.argtypes = [vp, ctypes.c_int32, vp]
+        lib.pca_posterior_mean.argtypes = [vp, vp, vp]
+        lib.pca_marginal_map.argtypes = [vp, vp, vp]
+        lib.pca_get_state.argtypes = [vp, vp, vp]
+        lib.pca_set_state.argtypes = [vp, vp, ctypes.c_int64, vp]
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.pca_stats.argtypes = [vp, i64p, i64p, i64p]
+        lib.pca_sync.argtypes = [vp]
+        lib.pca_destroy.argtypes = [vp]
+        lib.pca_last_error.argtypes = []
+        lib.pca_last_error.restype = ctypes.c_char_p
+        for name in EXPORTED[:-1]:
+            getattr(lib, name).restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def pca_last_error() -> str:
+    return load().pca_last_error().decode()
+
+
+def _check(rc: int, what: str):
+    if rc != PCA_OK:
+        raise PcaError(rc, what, pca_last_error())
+
+
+def make_params(*, height: int, width: int, levels: int, chains: int = 1, neighbourhood: int = 4,
+                prior: int = PCA_PRIOR_TRUNC_LINEAR, trunc: int = 1, J: float = 0.0, q: float = 0.0,
+                sigma: float = 1.0, vmin: float = 0.0, vmax: Optional[float] = None,
+                beta: Sequence[float] = (), seed: int = 0, init_mode: int = 0, burn_in: int = 0,
+                tally_stride: int = 0):
+    """A pca_params struct plus the beta buffer it points to (keep both alive)."""
+    if vmax is None:
+        vmax = float(levels - 1)
+    beta = list(beta)
+    buf = (ctypes.c_float * max(1, len(beta)))(*beta) if beta else None
+    p = pca_params(height, width, levels, chains, neighbourhood, prior, trunc, J, q, sigma, vmin, vmax,
+                   ctypes.cast(buf, ctypes.POINTER(ctypes.c_float)) if buf is not None else None, len(beta),
+                   seed & 0xFFFFFFFFFFFFFFFF, init_mode, burn_in, tally_stride)
+    return p, buf
+
+
+def pca_init(params: pca_params, obs_ptr: int, stream: int = 0) -> int:
+    ctx = ctypes.c_void_p()
+    _check(load().pca_init(ctypes.byref(params), ctypes.c_void_p(obs_ptr), ctypes.c_void_p(stream),
+                           ctypes.byref(ctx)), "pca_init")
+    return ctx.value
+
+
+def pca_sweep(ctx: int, n: int, stream: int = 0):
+    _check(load().pca_sweep(ctypes.c_void_p(ctx), int(n), ctypes.c_void_p(stream)), "pca_sweep")
+
+
+def pca_posterior_mean(ctx: int, out_ptr: int, stream: int = 0):
+    _check(load().pca_posterior_mean(ctypes.c_void_p(ctx), ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)),
+           "pca_posterior_mean")
+
+
+def pca_marginal_map(ctx: int, out_ptr: int, stream: int = 0):
+    _check(load().pca_marginal_map(ctypes.c_void_p(ctx), ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)),
+           "pca_marginal_map")
+
+
+def pca_get_state(ctx: int, out_ptr: int, stream: int = 0):
+    _check(load().pca_get_state(ctypes.c_void_p(ctx), ctypes.c_void_p(out_ptr), ctypes.c_void_p(stream)),
+           "pca_get_state")
+
+
+def pca_set_state(ctx: int, in_ptr: int, t: int, stream: int = 0):
+    _check(load().pca_set_state(ctypes.c_void_p(ctx), ctypes.c_void_p(in_ptr), int(t), ctypes.c_void_p(stream)),
+           "pca_set_state")
+
+
+def pca_stats(ctx: int):
+    s, c, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().pca_stats(ctypes.c_void_p(ctx), ctypes.byref(s), ctypes.byref(c), ctypes.byref(t)), "pca_stats")
+    return s.value, c.value, t.value
+
+
+def pca_sync(ctx: int):
+    _check(load().pca_sync(ctypes.c_void_p(ctx)), "pca_sync")
+
+
+def pca_destroy(ctx: int):
+    _check(load().pca_destroy(ctypes.c_void_p(ctx)), "pca_destroy")

@@ -1,0 +1,317 @@
+// C ABI of the lazy PCA sampler (declared in include/pca.h): parameter validation,
+// device memory, sweep bookkeeping (beta schedule, burn-in, tally sweeps) and error
+// reporting.  Every step of the sampler itself runs in the kernels of pca_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pca.h"
+#include "pca_internal.h"
+
+struct pca_ctx {
+    int device = 0;
+    pca_params p{};
+    std::vector<float> beta;
+    int G = 1, Cp = 1, T = 1;
+    int64_t N = 0;
+    int hist_words = 0;
+    float *gp = nullptr;
+    uint8_t *x[2] = {nullptr, nullptr};
+    int cur = 0;
+    uint32_t *sum = nullptr;
+    uint32_t *hist = nullptr;
+    int64_t t = 0, count = 0, tallies = 0;
+    hipStream_t last = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(PCA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int validate(const pca_params *p)
+{
+    if (!p) return fail(PCA_EINVAL, "params is NULL");
+    if (p->height < 1 || p->width < 1) return fail(PCA_EINVAL, "height and width must be >= 1");
+    if ((int64_t)p->height * p->width >= ((int64_t)1 << 31)) return fail(PCA_EINVAL, "lattice too large");
+    if (p->levels < 2 || p->levels > 256) return fail(PCA_EINVAL, "levels must be in [2, 256]");
+    if (p->chains < 1 || p->chains > 1024) return fail(PCA_EINVAL, "chains must be in [1, 1024]");
+    if (p->neighbourhood != 4 && p->neighbourhood != 8) return fail(PCA_EINVAL, "neighbourhood must be 4 or 8");
+    if (p->prior != PCA_PRIOR_POTTS && p->prior != PCA_PRIOR_TRUNC_LINEAR) return fail(PCA_EINVAL, "unknown prior");
+    if (p->prior == PCA_PRIOR_TRUNC_LINEAR && p->trunc < 1) return fail(PCA_EINVAL, "trunc must be >= 1");
+    if (!(p->J >= 0.0f) || !std::isfinite(p->J)) return fail(PCA_EINVAL, "J must be finite and >= 0");
+    if (!(p->q >= 0.0f) || !std::isfinite(p->q)) return fail(PCA_EINVAL, "q must be finite and >= 0");
+    if (!(p->sigma > 0.0f) || !std::isfinite(p->sigma)) return fail(PCA_EINVAL, "sigma must be finite and > 0");
+    if (!std::isfinite(p->vmin) || !std::isfinite(p->vmax) || !(p->vmax > p->vmin))
+        return fail(PCA_EINVAL, "need finite vmin < vmax");
+    if (p->beta_len < 0 || (p->beta_len > 0 && !p->beta)) return fail(PCA_EINVAL, "bad beta array");
+    const double log2e = pcak::kLog2e;
+    for (int i = 0; i < p->beta_len; ++i) {
+        if (!(p->beta[i] > 0.0f) || !std::isfinite(p->beta[i])) return fail(PCA_EINVAL, "beta[%d] must be > 0", i);
+        if ((double)p->beta[i] * (double)p->q * log2e > 100.0) return fail(PCA_EINVAL, "beta*q too large");
+    }
+    if (p->beta_len == 0 && (double)p->q * log2e > 100.0) return fail(PCA_EINVAL, "q too large");
+    if (p->init_mode != 0 && p->init_mode != 1) return fail(PCA_EINVAL, "init_mode must be 0 or 1");
+    if (p->burn_in < 0 || p->tally_stride < 0) return fail(PCA_EINVAL, "burn_in and tally_stride must be >= 0");
+    return PCA_OK;
+}
+
+double beta_at(const pca_ctx *ctx, int64_t t)
+{
+    if (ctx->beta.empty()) return 1.0;
+    if (t >= (int64_t)ctx->beta.size()) return (double)ctx->beta.back();
+    return (double)ctx->beta[(size_t)t];
+}
+
+double level_scale(const pca_params &p) { return (double)(p.levels - 1) / ((double)p.vmax - (double)p.vmin); }
+
+void release(pca_ctx *ctx)
+{
+    (void)hipFree(ctx->gp);
+    (void)hipFree(ctx->x[0]);
+    (void)hipFree(ctx->x[1]);
+    (void)hipFree(ctx->sum);
+    (void)hipFree(ctx->hist);
+    delete ctx;
+}
+
+int check_ctx(const pca_ctx *ctx)
+{
+    if (!ctx) return fail(PCA_EINVAL, "ctx is NULL");
+    return PCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pca_last_error(void) { return g_err.c_str(); }
+
+int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_ctx **out)
+{
+    g_err.clear();
+    if (!out) return fail(PCA_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate(params);
+    if (rc) return rc;
+    if (!obs_dev) return fail(PCA_EINVAL, "obs_dev is NULL");
+    hipStream_t s = (hipStream_t)stream;
+
+    pca_ctx *ctx = new pca_ctx();
+    ctx->p = *params;
+    if (params->beta_len > 0) ctx->beta.assign(params->beta, params->beta + params->beta_len);
+    ctx->p.beta = nullptr;
+    (void)hipGetDevice(&ctx->device);
+    ctx->G = pcak::chain_group(params->chains);
+    ctx->Cp = (params->chains + ctx->G - 1) / ctx->G * ctx->G;
+    ctx->T = params->prior == PCA_PRIOR_POTTS ? 1 : (params->trunc < params->levels - 1 ? params->trunc
+                                                                                         : params->levels - 1);
+    ctx->N = (int64_t)params->height * params->width;
+    ctx->hist_words = (params->levels + 1) / 2;
+    ctx->last = s;
+    if ((ctx->N * (ctx->Cp / ctx->G) + pcak::kBlock - 1) / pcak::kBlock > 0x7FFFFFFF) {
+        delete ctx;
+        return fail(PCA_EINVAL, "lattice times chains too large for one launch");
+    }
+
+    const size_t N = (size_t)ctx->N;
+    hipError_t e = hipMalloc(&ctx->gp, N * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&ctx->x[0], N * ctx->Cp);
+    if (e == hipSuccess) e = hipMalloc(&ctx->x[1], N * ctx->Cp);
+    if (e == hipSuccess) e = hipMalloc(&ctx->sum, N * sizeof(uint32_t));
+    if (e == hipSuccess && params->tally_stride > 0) e = hipMalloc(&ctx->hist, N * ctx->hist_words * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release(ctx);
+        return fail(PCA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    e = hipMemsetAsync(ctx->sum, 0, N * sizeof(uint32_t), s);
+    if (e == hipSuccess && ctx->hist) e = hipMemsetAsync(ctx->hist, 0, N * ctx->hist_words * sizeof(uint32_t), s);
+    if (e == hipSuccess) {
+        pcak::InitArgs a{};
+        a.obs = obs_dev;
+        a.gp = ctx->gp;
+        a.x = ctx->x[0];
+        a.N = ctx->N;
+        a.Cp = ctx->Cp;
+        a.L = params->levels;
+        a.mode = params->init_mode;
+        a.vmin = (double)params->vmin;
+        a.scale = level_scale(*params);
+        a.key0 = (uint32_t)params->seed;
+        a.key1 = (uint32_t)(params->seed >> 32);
+        e = pcak::launch_init(a, s);
+    }
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
+        release(ctx);
+        return hip_fail(e, "pca_init");
+    }
+    *out = ctx;
+    return PCA_OK;
+}
+
+int pca_sweep(pca_ctx *ctx, int32_t n, void *stream)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (n < 0) return fail(PCA_EINVAL, "n must be >= 0");
+    if (n == 0) return PCA_OK;
+    const pca_params &p = ctx->p;
+    // Overflow guards: the uint32 level sum and the uint16 histogram counters.
+    int64_t add_count = 0, add_tallies = 0;
+    for (int64_t t = ctx->t; t < ctx->t + n; ++t) {
+        if (t >= p.burn_in) {
+            add_count += p.chains;
+            if (p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0) add_tallies += 1;
+        }
+    }
+    if ((double)(ctx->count + add_count) * (double)(p.levels - 1) > 4294967295.0)
+        return fail(PCA_ESTATE, "the level sum could overflow 32 bits");
+    if ((ctx->tallies + add_tallies) * (int64_t)p.chains > 65535)
+        return fail(PCA_ESTATE, "a histogram counter could overflow 16 bits");
+
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    pcak::SweepArgs a{};
+    a.gp = ctx->gp;
+    a.H = p.height;
+    a.W = p.width;
+    a.L = p.levels;
+    a.C = p.chains;
+    a.Cp = ctx->Cp;
+    a.T = ctx->T;
+    a.hist_words = ctx->hist_words;
+    a.J = (double)p.J;
+    a.q = (double)p.q;
+    a.kappa = p.prior == PCA_PRIOR_POTTS ? 2.0 : 1.0;
+    a.sigma_s = (double)p.sigma * level_scale(p);
+    a.key0 = (uint32_t)p.seed;
+    a.key1 = (uint32_t)(p.seed >> 32);
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t t = ctx->t;
+        const bool acc = t >= p.burn_in;
+        const bool tally = acc && p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0;
+        a.xin = ctx->x[ctx->cur];
+        a.xout = ctx->x[ctx->cur ^ 1];
+        a.sum = acc ? ctx->sum : nullptr;
+        a.hist = tally ? ctx->hist : nullptr;
+        a.beta = beta_at(ctx, t);
+        a.t = (uint32_t)t;
+        hipError_t e = pcak::launch_sweep(a, ctx->G, p.neighbourhood, s);
+        if (e != hipSuccess) return hip_fail(e, "pca_sweep");
+        ctx->cur ^= 1;
+        ctx->t += 1;
+        if (acc) ctx->count += p.chains;
+        if (tally) ctx->tallies += 1;
+    }
+    return PCA_OK;
+}
+
+int pca_posterior_mean(pca_ctx *ctx, float *out_dev, void *stream)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out_dev) return fail(PCA_EINVAL, "out_dev is NULL");
+    if (ctx->count <= 0) return fail(PCA_ESTATE, "no accumulated sweeps");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    const pca_params &p = ctx->p;
+    const double delta = ((double)p.vmax - (double)p.vmin) / (double)(p.levels - 1);
+    hipError_t e = pcak::launch_mean(ctx->sum, out_dev, ctx->N, ctx->count, (double)p.vmin, delta, s);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_posterior_mean");
+}
+
+int pca_marginal_map(pca_ctx *ctx, uint8_t *out_dev, void *stream)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out_dev) return fail(PCA_EINVAL, "out_dev is NULL");
+    if (!ctx->hist) return fail(PCA_ESTATE, "histogram disabled (tally_stride = 0)");
+    if (ctx->tallies <= 0) return fail(PCA_ESTATE, "no tally sweeps yet");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    hipError_t e = pcak::launch_mpm(ctx->hist, out_dev, ctx->N, ctx->p.levels, ctx->hist_words, s);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_marginal_map");
+}
+
+int pca_get_state(pca_ctx *ctx, uint8_t *out_dev, void *stream)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out_dev) return fail(PCA_EINVAL, "out_dev is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    hipError_t e = pcak::launch_get_state(ctx->x[ctx->cur], out_dev, ctx->N, ctx->p.chains, ctx->Cp, s);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_get_state");
+}
+
+int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!in_dev) return fail(PCA_EINVAL, "in_dev is NULL");
+    if (t < 0 || t > 0xFFFFFFFFll) return fail(PCA_EINVAL, "t out of range");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    hipError_t e = pcak::launch_set_state(in_dev, ctx->x[ctx->cur], ctx->N, ctx->p.chains, ctx->Cp, ctx->p.levels, s);
+    if (e != hipSuccess) return hip_fail(e, "pca_set_state");
+    ctx->t = t;
+    return PCA_OK;
+}
+
+int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *tallies)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (sweep) *sweep = ctx->t;
+    if (count) *count = ctx->count;
+    if (tallies) *tallies = ctx->tallies;
+    return PCA_OK;
+}
+
+int pca_sync(pca_ctx *ctx)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(ctx->last);
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_sync");
+}
+
+int pca_destroy(pca_ctx *ctx)
+{
+    g_err.clear();
+    if (!ctx) return PCA_OK;
+    hipError_t e = hipStreamSynchronize(ctx->last);
+    release(ctx);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_destroy");
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+// Internal interface between the C-ABI layer (pca_api.hip) and the gfx950 kernels
+// (pca_kernels.hip).  Not part of the public boundary; see include/pca.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcak {
+
+constexpr int kBlock = 256;                 // threads per workgroup (4 wave64)
+constexpr int kMaxNeighbourStat = 8 * 255;  // largest S = sum_j min(|k-x_j|, T) over 8 neighbours
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+
+// Scalars of one sweep launch.  Doubles are the run parameters; the kernel derives its
+// FP32 constants from them with a fixed operation order.
+struct SweepArgs {
+    const float *gp;      // [N] observation in level units
+    const uint8_t *xin;   // [N][Cp] state at sweep t (chain-interleaved)
+    uint8_t *xout;        // [N][Cp] state at sweep t+1
+    uint32_t *sum;        // [N] level sums over chains and sweeps, or nullptr (not accumulated)
+    uint32_t *hist;       // [N][hist_words] packed uint16 level counters, or nullptr
+    int H, W, L, C, Cp;   // Cp = chains rounded up to the per-thread chain group
+    int T;                // effective truncation (1 for Potts, min(trunc, L-1) otherwise)
+    int hist_words;       // (L + 1) / 2
+    double beta, J, q, kappa, sigma_s;  // kappa = 2 (Potts) or 1; sigma_s = sigma in level units
+    uint32_t key0, key1;  // Philox key (seed split)
+    uint32_t t;           // sweep index
+};
+
+struct InitArgs {
+    const float *obs;  // [N] value units
+    float *gp;         // [N] level units
+    uint8_t *x;        // [N][Cp]
+    int64_t N;
+    int Cp, L, mode;
+    double vmin, scale;
+    uint32_t key0, key1;
+};
+
+// Chains handled by one thread: 4 (one Philox call feeds four chains) unless fewer exist.
+inline int chain_group(int chains) { return chains >= 3 ? 4 : chains; }
+
+hipError_t launch_init(const InitArgs &a, hipStream_t s);
+hipError_t launch_sweep(const SweepArgs &a, int G, int nbr, hipStream_t s);
+hipError_t launch_get_state(const uint8_t *x, uint8_t *out, int64_t N, int C, int Cp, hipStream_t s);
+hipError_t launch_set_state(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp, int L, hipStream_t s);
+hipError_t launch_mean(const uint32_t *sum, float *out, int64_t N, int64_t count, double vmin, double delta,
+                       hipStream_t s);
+hipError_t launch_mpm(const uint32_t *hist, uint8_t *out, int64_t N, int L, int hist_words, hipStream_t s);
+
+}  // namespace pcak

@@ -1,0 +1,443 @@
+// gfx950 kernels of the lazy PCA sampler (Costarelli, Piconi, Troiani, arXiv 2507.14869,
+// Sec. 5.2).  The path is bound by vector ALU work (L level evaluations per site
+// update), so the kernels are written for VALU throughput: no MFMA (there is no dense
+// contraction), one thread per (pixel, group of up to four chains), chain-interleaved
+// uint8 state so one dword load brings a pixel's four chain values, the neighbour
+// statistic from byte-wise sums of absolute differences, and the per-sweep prior
+// factor table in LDS.
+//
+// Arithmetic of one site update (identical, operation for operation, to the written
+// convention the CPU reference follows; FP32, round to nearest even, no implicit
+// contraction - the file is built with -ffp-contract=off):
+//   exp2s(y)  = 0 if y < -125, else ldexp(p(f), n) with n = rint(y), f = y - n and p the
+//               degree-6 Taylor polynomial of 2^f (coefficients (float)(ln2^k / k!), the
+//               double values built as t_k = (t_{k-1} * ln2) / k), evaluated by fma Horner.
+//   D_k       = exp2s(fma(-a2, e_k*e_k, m)), e_k = g' - k, m = a2*(e0*e0), e0 = g' - khat,
+//               khat = clamp(rint(g'), 0, L-1), a2 = (float)(log2e / ((2 s) s)), s = sigma
+//               in level units: the Gaussian data term of Sec. 4, not scaled by beta.
+//   P(S)      = exp2s(-(c2 * S)), c2 = (float)(((beta*J)*kappa)*log2e), S = sum over
+//               in-lattice neighbours of min(|k - x_j|, T): the pair prior (Potts counts
+//               disagreeing neighbours with kappa = 2, T = 1).
+//   R         = exp2s((float)((beta*q)*log2e)) - 1: the inertia of Sec. 5.2 written as an
+//               extra "stay" weight, P(k|x) ~ D_k P(S_k) + [k = x] D_x P(S_x) R.
+//   acc_{-1}  = (D_x * P(S_x)) * R, acc_k = fma(D_k, P(S_k), acc_{k-1}), Z = acc_{L-1}.
+//   draw      = x if acc_{-1} > u Z, else the least k with acc_k > u Z (exact comparison,
+//               done as acc > RD(u Z)); x if Z == 0.  u = (r >> 8) 2^-24, r the chain's
+//               Philox4x32-10 word for counter {pixel, t, chain/4, 0}.
+#include "pca_internal.h"
+
+namespace pcak {
+namespace {
+
+// ---------------------------------------------------------------- exp2s
+
+constexpr double taylor_coeff(int k)
+{
+    double t = 1.0;
+    for (int i = 1; i <= k; ++i) t = (t * kLn2) / (double)i;
+    return t;
+}
+
+constexpr float kP0 = (float)taylor_coeff(0);
+constexpr float kP1 = (float)taylor_coeff(1);
+constexpr float kP2 = (float)taylor_coeff(2);
+constexpr float kP3 = (float)taylor_coeff(3);
+constexpr float kP4 = (float)taylor_coeff(4);
+constexpr float kP5 = (float)taylor_coeff(5);
+constexpr float kP6 = (float)taylor_coeff(6);
+
+__device__ __forceinline__ float exp2s(float y)
+{
+    const float n = __builtin_rintf(y);
+    const float f = y - n;
+    float p = kP6;
+    p = __builtin_fmaf(p, f, kP5);
+    p = __builtin_fmaf(p, f, kP4);
+    p = __builtin_fmaf(p, f, kP3);
+    p = __builtin_fmaf(p, f, kP2);
+    p = __builtin_fmaf(p, f, kP1);
+    p = __builtin_fmaf(p, f, kP0);
+    const float r = __builtin_amdgcn_ldexpf(p, (int)n);
+    return y < -125.0f ? 0.0f : r;
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t word_of(const U4 &r, int i)
+{
+    return i == 0 ? r.x : i == 1 ? r.y : i == 2 ? r.z : r.w;
+}
+
+// Round-down of the exact product u*Z (both FP32, exact in double).
+__device__ __forceinline__ float threshold_rd(float u, float Z)
+{
+    const double t = (double)u * (double)Z;
+    float f = (float)t;
+    if ((double)f > t) f = __uint_as_float(__float_as_uint(f) - 1u);  // f > t >= 0
+    return f;
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t load_group(const uint8_t *p)
+{
+    if constexpr (G == 4) return *reinterpret_cast<const uint32_t *>(p);
+    else if constexpr (G == 2) return *reinterpret_cast<const uint16_t *>(p);
+    else return *p;
+}
+
+template <int G>
+__device__ __forceinline__ void store_group(uint8_t *p, uint32_t v)
+{
+    if constexpr (G == 4) *reinterpret_cast<uint32_t *>(p) = v;
+    else if constexpr (G == 2) *reinterpret_cast<uint16_t *>(p) = (uint16_t)v;
+    else *p = (uint8_t)v;
+}
+
+// ---------------------------------------------------------------- sweep
+
+// Per-chain neighbour data for the byte-wise statistic.  With lo_j = max(x_j - T_j, 0),
+// hi_j = min(x_j + T_j, 255) and T_j = 0 for absent neighbours, for every k in [0, 255]
+//   2 min(|k - x_j|, T_j) = 2|k - x_j| - |k - hi_j| - |k - lo_j| + (hi_j - lo_j),
+// so 2S_k = 2 SAD(k, x) - SAD(k, hi) - SAD(k, lo) + sum_j (hi_j - lo_j), each SAD one
+// v_sad_u8 over four neighbours packed in a dword.
+template <int NW>
+struct NbrPack {
+    uint32_t x[NW], lo[NW], hi[NW];
+    int cb;  // 2 * sum_j (hi_j - lo_j): byte offset term of the table address
+};
+
+template <int NW>
+__device__ __forceinline__ float prior_lookup(const char *ptab, const NbrPack<NW> &nb, uint32_t kk)
+{
+    uint32_t u = 0, v = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        u = __builtin_amdgcn_sad_u8(kk, nb.x[w], u);
+        v = __builtin_amdgcn_sad_u8(kk, nb.lo[w], v);
+        v = __builtin_amdgcn_sad_u8(kk, nb.hi[w], v);
+    }
+    // byte offset 4 S = 4u - 2v + 2 sum(hi - lo)
+    const int off = (int)(4u * u) - (int)(2u * v) + nb.cb;
+    return *reinterpret_cast<const float *>(ptab + off);
+}
+
+template <int G, int NBR, int SUB, int NBLK>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
+{
+    constexpr int NW = NBR / 4;
+    __shared__ float ptab[kMaxNeighbourStat + 1];
+
+    // Per-sweep constants, same for every thread.
+    const float c2 = (float)(((a.beta * a.J) * a.kappa) * kLog2e);
+    const float q2 = (float)((a.beta * a.q) * kLog2e);
+    const float R = exp2s(q2) - 1.0f;
+    const float a2 = (float)(kLog2e / ((2.0 * a.sigma_s) * a.sigma_s));
+    const int nP = NBR * a.T + 1;
+    for (int s = threadIdx.x; s < nP; s += kBlock) ptab[s] = exp2s(-(c2 * (float)s));
+    __syncthreads();
+
+    const int tpp = a.Cp / G;
+    const int64_t N = (int64_t)a.H * a.W;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= N * tpp) return;
+    const int pix = (int)(gid / tpp);
+    const int grp = (int)(gid - (int64_t)pix * tpp);
+    const int r = pix / a.W;
+    const int c = pix - r * a.W;
+    const int cofs = grp * G;
+    const int L = a.L;
+
+    // Observation and the data-term shift.
+    const float gp = a.gp[pix];
+    float khat = __builtin_rintf(gp);
+    khat = khat < 0.0f ? 0.0f : khat;
+    khat = khat > (float)(L - 1) ? (float)(L - 1) : khat;
+    const float e0 = gp - khat;
+    const float m = a2 * (e0 * e0);
+
+    // State words of the pixel and its neighbours (G chains each).
+    const uint8_t *xin = a.xin;
+    const uint32_t own = load_group<G>(xin + (int64_t)pix * a.Cp + cofs);
+    uint32_t nbw[NBR];
+    bool present[NBR];
+    {
+        const int dr[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
+        const int dc[8] = {0, 0, -1, 1, -1, 1, -1, 1};
+#pragma unroll
+        for (int j = 0; j < NBR; ++j) {
+            const int rr = r + dr[j], cc = c + dc[j];
+            present[j] = rr >= 0 && rr < a.H && cc >= 0 && cc < a.W;
+            nbw[j] = present[j] ? load_group<G>(xin + ((int64_t)rr * a.W + cc) * a.Cp + cofs) : 0u;
+        }
+    }
+
+    const char *pt = reinterpret_cast<const char *>(ptab);
+    NbrPack<NW> nb[G];
+    int xs[G];
+    float stay[G], acc[G];
+#pragma unroll
+    for (int ch = 0; ch < G; ++ch) {
+        xs[ch] = (int)((own >> (8 * ch)) & 0xFFu);
+        int csum = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            nb[ch].x[w] = nb[ch].lo[w] = nb[ch].hi[w] = 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < NBR; ++j) {
+            const int xj = (int)((nbw[j] >> (8 * ch)) & 0xFFu);
+            const int Tj = present[j] ? a.T : 0;
+            const int lo = xj > Tj ? xj - Tj : 0;
+            const int hi = xj + Tj < 255 ? xj + Tj : 255;
+            csum += hi - lo;
+            nb[ch].x[j / 4] |= (uint32_t)xj << (8 * (j % 4));
+            nb[ch].lo[j / 4] |= (uint32_t)lo << (8 * (j % 4));
+            nb[ch].hi[j / 4] |= (uint32_t)hi << (8 * (j % 4));
+        }
+        nb[ch].cb = 2 * csum;
+        // Stay weight of the lazy conditional.
+        const float ex = gp - (float)xs[ch];
+        const float Dx = exp2s(__builtin_fmaf(-a2, ex * ex, m));
+        const float Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)xs[ch] * 0x01010101u);
+        stay[ch] = (Dx * Px) * R;
+        acc[ch] = stay[ch];
+    }
+
+    // Main pass over levels, keeping the running sum at the end of every block.
+    float part[NBLK][G];
+    const int nblk = (L + SUB - 1) / SUB;
+    uint32_t kk = 0u;
+    float kf = 0.0f;
+#pragma unroll
+    for (int b = 0; b < NBLK; ++b) {
+        if (b < nblk) {
+            const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
+            for (int i = 0; i < kend; ++i) {
+                const float e = gp - kf;
+                const float D = exp2s(__builtin_fmaf(-a2, e * e, m));
+#pragma unroll
+                for (int ch = 0; ch < G; ++ch) {
+                    const float P = prior_lookup<NW>(pt, nb[ch], kk);
+                    acc[ch] = __builtin_fmaf(D, P, acc[ch]);
+                }
+                kk += 0x01010101u;
+                kf += 1.0f;
+            }
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
+        }
+    }
+
+    // Inverse-CDF draw for each chain.
+    const int chain0 = cofs;
+    const U4 rnd = philox(U4{(uint32_t)pix, a.t, (uint32_t)(chain0 >> 2), 0u}, a.key0, a.key1);
+    uint32_t packed = 0u;
+    uint32_t lsum = 0u;
+    int knew[G];
+#pragma unroll
+    for (int ch = 0; ch < G; ++ch) {
+        const uint32_t w = word_of(rnd, (chain0 & 3) + ch);
+        const float u = (float)(w >> 8) * 0x1p-24f;
+        const float Z = acc[ch];
+        int k = xs[ch];
+        if (Z != 0.0f) {
+            const float tf = threshold_rd(u, Z);
+            if (!(stay[ch] > tf)) {
+                int bsel = nblk - 1;
+                float start = 0.0f;
+#pragma unroll
+                for (int b = NBLK - 1; b >= 0; --b) {
+                    if (b < nblk && part[b][ch] > tf) {
+                        bsel = b;
+                        start = b == 0 ? stay[ch] : part[b > 0 ? b - 1 : 0][ch];
+                    }
+                }
+                if constexpr (SUB == 1) {
+                    k = bsel;
+                } else {
+                    // Re-run the sums of the selected block; they reproduce the main pass exactly.
+                    const int k0 = bsel * SUB;
+                    const int kend = (L - k0) < SUB ? (L - k0) : SUB;
+                    float s = start;
+                    k = k0 + kend - 1;
+                    uint32_t kk2 = (uint32_t)k0 * 0x01010101u;
+                    for (int i = 0; i < kend; ++i) {
+                        const float e = gp - (float)(k0 + i);
+                        const float D = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        const float P = prior_lookup<NW>(pt, nb[ch], kk2);
+                        s = __builtin_fmaf(D, P, s);
+                        if (s > tf) {
+                            k = k0 + i;
+                            break;
+                        }
+                        kk2 += 0x01010101u;
+                    }
+                }
+            }
+        }
+        knew[ch] = k;
+        packed |= (uint32_t)k << (8 * ch);
+        if (chain0 + ch < a.C) lsum += (uint32_t)k;
+    }
+    store_group<G>(a.xout + (int64_t)pix * a.Cp + cofs, packed);
+
+    if (a.sum) {
+        if (tpp == 1) a.sum[pix] += lsum;
+        else atomicAdd(a.sum + pix, lsum);
+    }
+    if (a.hist) {
+        uint32_t *hrow = a.hist + (int64_t)pix * a.hist_words;
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch) {
+            if (chain0 + ch < a.C) atomicAdd(hrow + (knew[ch] >> 1), 1u << (16 * (knew[ch] & 1)));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- init and readouts
+
+__global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a)
+{
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= a.N) return;
+    const float gp = (float)(((double)a.obs[pix] - a.vmin) * a.scale);
+    a.gp[pix] = gp;
+    float kh = __builtin_rintf(gp);
+    kh = kh < 0.0f ? 0.0f : kh;
+    kh = kh > (float)(a.L - 1) ? (float)(a.L - 1) : kh;
+    uint8_t *row = a.x + pix * a.Cp;
+    for (int c0 = 0; c0 < a.Cp; c0 += 4) {
+        U4 rnd{0u, 0u, 0u, 0u};
+        if (a.mode == 1) rnd = philox(U4{(uint32_t)pix, 0u, (uint32_t)(c0 >> 2), 1u}, a.key0, a.key1);
+        for (int j = 0; j < 4 && c0 + j < a.Cp; ++j) {
+            int v;
+            if (a.mode == 0) v = (int)kh;
+            else v = (int)(((uint64_t)(word_of(rnd, j) >> 8) * (uint64_t)a.L) >> 24);
+            row[c0 + j] = (uint8_t)v;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void get_state_kernel(const uint8_t *x, uint8_t *out, int64_t N, int C, int Cp)
+{
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= N) return;
+    for (int ch = 0; ch < C; ++ch) out[(int64_t)ch * N + pix] = x[pix * Cp + ch];
+}
+
+__global__ __launch_bounds__(kBlock) void set_state_kernel(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp,
+                                                           int L)
+{
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= N) return;
+    for (int ch = 0; ch < Cp; ++ch) {
+        const int src = ch < C ? ch : 0;
+        const int v = in[(int64_t)src * N + pix];
+        x[pix * Cp + ch] = (uint8_t)(v < L ? v : L - 1);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void mean_kernel(const uint32_t *sum, float *out, int64_t N, int64_t count,
+                                                      double vmin, double delta)
+{
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= N) return;
+    out[pix] = (float)(vmin + ((double)sum[pix] / (double)count) * delta);
+}
+
+__global__ __launch_bounds__(kBlock) void mpm_kernel(const uint32_t *hist, uint8_t *out, int64_t N, int L,
+                                                     int hist_words)
+{
+    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (pix >= N) return;
+    const uint32_t *h = hist + pix * hist_words;
+    int best = 0;
+    uint32_t bestv = h[0] & 0xFFFFu;
+    for (int k = 1; k < L; ++k) {
+        const uint32_t v = (h[k >> 1] >> (16 * (k & 1))) & 0xFFFFu;
+        if (v > bestv) {
+            bestv = v;
+            best = k;
+        }
+    }
+    out[pix] = (uint8_t)best;
+}
+
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+template <int G, int NBR>
+hipError_t launch_sweep_g(const SweepArgs &a, hipStream_t s)
+{
+    const int64_t threads = (int64_t)a.H * a.W * (a.Cp / G);
+    if (a.L <= 16)
+        hipLaunchKernelGGL((sweep_kernel<G, NBR, 1, 16>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
+    else
+        hipLaunchKernelGGL((sweep_kernel<G, NBR, 16, 16>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sweep(const SweepArgs &a, int G, int nbr, hipStream_t s)
+{
+    if (nbr == 4) {
+        if (G == 4) return launch_sweep_g<4, 4>(a, s);
+        if (G == 2) return launch_sweep_g<2, 4>(a, s);
+        return launch_sweep_g<1, 4>(a, s);
+    }
+    if (G == 4) return launch_sweep_g<4, 8>(a, s);
+    if (G == 2) return launch_sweep_g<2, 8>(a, s);
+    return launch_sweep_g<1, 8>(a, s);
+}
+
+hipError_t launch_init(const InitArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(init_kernel, dim3(grid_for(a.N)), dim3(kBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_get_state(const uint8_t *x, uint8_t *out, int64_t N, int C, int Cp, hipStream_t s)
+{
+    hipLaunchKernelGGL(get_state_kernel, dim3(grid_for(N)), dim3(kBlock), 0, s, x, out, N, C, Cp);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_state(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp, int L, hipStream_t s)
+{
+    hipLaunchKernelGGL(set_state_kernel, dim3(grid_for(N)), dim3(kBlock), 0, s, in, x, N, C, Cp, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_mean(const uint32_t *sum, float *out, int64_t N, int64_t count, double vmin, double delta,
+                       hipStream_t s)
+{
+    hipLaunchKernelGGL(mean_kernel, dim3(grid_for(N)), dim3(kBlock), 0, s, sum, out, N, count, vmin, delta);
+    return hipGetLastError();
+}
+
+hipError_t launch_mpm(const uint32_t *hist, uint8_t *out, int64_t N, int L, int hist_words, hipStream_t s)
+{
+    hipLaunchKernelGGL(mpm_kernel, dim3(grid_for(N)), dim3(kBlock), 0, s, hist, out, N, L, hist_words);
+    return hipGetLastError();
+}
+
+}  // namespace pcak

@@ -1,0 +1,163 @@
+"""HIP path vs the CPU oracle, through the C ABI, on seeded synthetic inputs.
+
+Integer state trajectories must agree bit for bit (the arithmetic is the same FP32
+convention on both sides; a threshold tie would show up as a mismatch and is allowed
+at most once per 1e6 site updates).  Posterior means and marginal modes are integer
+sums turned into values by one rounding, so they must agree exactly.
+"""
+import numpy as np
+import pytest
+
+try:  # import at collection so the first GPU test's time limit does not include it
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+from tests.gpu_util import gpu_sampler, oracle_run, stepwise, torch_cuda
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+FLIP_BUDGET = 1e-6
+
+
+def _obs(H, W, L, seed, vmin=0.0, vmax=None, sigma=None):
+    vmax = float(L - 1) if vmax is None else vmax
+    rng = np.random.default_rng(seed)
+    truth = synth.random_image(H, W, L, max(2, H * W // 400), L > 2, rng)
+    sigma = 0.2 * (vmax - vmin) if sigma is None else sigma
+    return synth.noisy_observation(truth, L, vmin, vmax, sigma, rng)
+
+
+def test_c1_free_running_200_sweeps(orc):
+    """64x64 binary Ising/Potts image, 1 chain, 200 sweeps: full trajectory, mean and mode."""
+    wl = synth.make_workload("c1")
+    kw = wl.params()
+    ref = oracle_run(orc, wl.obs, **kw).sweep(wl.sweeps)
+    gpu = gpu_sampler(wl.obs, **kw).sweep(wl.sweeps)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+    assert gpu.stats() == (200, 150, 150)
+
+
+@pytest.mark.parametrize("case", [
+    # (H, W, L, chains, nbr, prior, T, J, q, sigma)
+    (96, 80, 16, 8, 4, 1, 4, 0.4, 1.5, 2.0),      # c2-shaped, 2 threads per pixel
+    (37, 41, 256, 16, 4, 1, 32, 0.05, 1.0, 20.0),  # c3-shaped, 4 threads per pixel
+    (30, 29, 5, 3, 8, 0, 1, 1 / 3, 0.51, 1.0),     # paper-like 8-neighbour Potts, padded chain
+    (23, 19, 33, 1, 8, 1, 3, 0.3, 0.7, 3.0),       # one chain per thread, partial last block
+    (17, 26, 33, 2, 4, 1, 40, 0.2, 0.3, 4.0),      # two chains, truncation above L-1
+    (12, 12, 2, 5, 4, 0, 1, 0.8, 2.0, 0.3),        # binary, 5 chains
+    (9, 14, 200, 4, 8, 1, 9, 0.1, 0.0, 15.0),      # q = 0: naive synchronous update
+    (16, 16, 16, 4, 4, 1, 4, 0.0, 1.0, 2.0),       # J = 0: independent sites
+])
+def test_stepwise_parity(orc, case):
+    H, W, L, C, nbr, prior, T, J, q, sigma = case
+    obs = _obs(H, W, L, seed=H * 1000 + W, sigma=sigma)
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=nbr, prior=prior, trunc=T, J=J, q=q,
+              sigma=sigma, vmin=0.0, vmax=float(L - 1), beta=[1.25] * 2 + [1.5] * 2 + [2.0], seed=4242 + H,
+              burn_in=1, tally_stride=2)
+    bad, total, ref, gpu = stepwise(orc, obs, 6, **kw)
+    assert bad <= FLIP_BUDGET * total, f"{bad} of {total} site updates differ"
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 37), (29, 1), (2, 2), (3, 300), (257, 3)])
+def test_degenerate_lattices_free_running(orc, shape):
+    H, W = shape
+    L = 7
+    obs = _obs(H, W, L, seed=7 + H + W)
+    kw = dict(height=H, width=W, levels=L, chains=6, neighbourhood=8, prior=1, trunc=2, J=0.5, q=0.8, sigma=1.4,
+              vmin=0.0, vmax=6.0, seed=99, init_mode=1, tally_stride=1)
+    ref = oracle_run(orc, obs, **kw).sweep(12)
+    gpu = gpu_sampler(obs, **kw).sweep(12)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+
+
+def test_value_units_and_random_init(orc):
+    """Observation in value units [-3, 5] with L = 9; random initial states."""
+    H, W, L = 40, 33, 9
+    obs = _obs(H, W, L, seed=5, vmin=-3.0, vmax=5.0, sigma=1.1)
+    kw = dict(height=H, width=W, levels=L, chains=4, prior=1, trunc=3, J=0.35, q=0.9, sigma=1.1, vmin=-3.0,
+              vmax=5.0, seed=(1 << 63) + 12345, init_mode=1, burn_in=3, tally_stride=1)
+    ref = oracle_run(orc, obs, **kw)
+    gpu = gpu_sampler(obs, **kw)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    ref.sweep(20)
+    gpu.sweep(20)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+
+
+def test_sweep_splitting_is_invisible(orc):
+    wl = synth.make_workload("c2", height=64, width=48, chains=8)
+    kw = wl.params(beta=[1.0, 1.5, 2.0], burn_in=2)
+    a = gpu_sampler(wl.obs, **kw).sweep(3).sweep(4).sweep(0)
+    b = gpu_sampler(wl.obs, **kw).sweep(7)
+    assert np.array_equal(a.state().cpu().numpy(), b.state().cpu().numpy())
+    assert np.array_equal(a.posterior_mean().cpu().numpy(), b.posterior_mean().cpu().numpy())
+    assert np.array_equal(a.marginal_map().cpu().numpy(), b.marginal_map().cpu().numpy())
+
+
+def test_chain_results_do_not_depend_on_chain_count():
+    wl = synth.make_workload("c2", height=40, width=40)
+    s16 = gpu_sampler(wl.obs, **wl.params(chains=16)).sweep(5).state().cpu().numpy()
+    s3 = gpu_sampler(wl.obs, **wl.params(chains=3)).sweep(5).state().cpu().numpy()
+    s1 = gpu_sampler(wl.obs, **wl.params(chains=1)).sweep(5).state().cpu().numpy()
+    assert np.array_equal(s16[:3], s3) and np.array_equal(s16[:1], s1)
+
+
+def test_streams_and_errors():
+    torch = torch_cuda()
+    from paper_2507_14869_amd import PcaError
+    wl = synth.make_workload("c2", height=32, width=32)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        g = gpu_sampler(wl.obs, **wl.params(burn_in=5))
+        g.sweep(3)
+        with pytest.raises(PcaError):
+            g.posterior_mean()  # nothing accumulated before burn-in
+        with pytest.raises(PcaError):
+            g.marginal_map()
+        with pytest.raises(PcaError):
+            g.sweep(-1)
+        g.sweep(3)
+        m = g.posterior_mean()
+    s.synchronize()
+    assert torch.isfinite(m).all()
+    g.sync()
+    g.close()
+
+
+def test_full_size_c3_sampled_sites(orc):
+    """2048x2048, L = 256, 16 chains in the benchmark's launch configuration: one sweep from
+    the oracle's initial state and one from an oracle-made random state at sweep 777,
+    checked at 3000 sampled (chain, pixel) sites each, plus the mean accumulator."""
+    torch = torch_cuda()
+    wl = synth.make_workload("c3")
+    kw = wl.params(burn_in=0)
+    p = orc.Params(**kw)
+    gpu = gpu_sampler(wl.obs, **kw)
+    x0 = orc.init_state(p, wl.obs)
+    assert np.array_equal(gpu.state().cpu().numpy(), x0)
+    rng = np.random.default_rng(31)
+    N = wl.height * wl.width
+    for t, start in ((0, x0), (777, None)):
+        if start is None:
+            start = rng.integers(0, 256, size=x0.shape, dtype=np.uint8)
+            gpu.set_state(torch.from_numpy(start).cuda(), t)
+        gpu.sweep(1)
+        got = gpu.state().cpu().numpy()
+        chains = rng.integers(0, 16, size=3000).astype(np.int32)
+        pix = rng.integers(0, N, size=3000).astype(np.int64)
+        # include the lattice corners and edges
+        pix[:4] = [0, wl.width - 1, N - wl.width, N - 1]
+        want = orc.update_sites(p, wl.obs, start, t, chains, pix)
+        assert np.array_equal(got.reshape(16, -1)[chains, pix], want)
+    # the mean accumulator holds exactly the sum of the two accumulated states
+    _, count, _ = gpu.stats()
+    assert count == 32

@@ -15,7 +15,7 @@ Named workloads (sizes, level counts, noise, priors, chains and sweeps):
       J 0.05, q 1.0, 16 chains, 1000 sweeps, posterior mean and marginal MAP.
   c4  batch of 64 images with log-uniform sides in [128, 1024] and mixed L (batch_mix).
   c5  Poisson request trace at 50 req/s with sides in [64, 4096] (serving_trace).
-Data seed 1000 + index, sampler seed 2000 + index.
+Data seed 1000 + index, sampler seed 2000 + index; burn-in is a quarter of the sweeps.
 """
 from __future__ import annotations
 
@@ -148,6 +148,7 @@ def make_workload(name: str, *, height: Optional[int] = None, width: Optional[in
         cfg["chains"] = chains
     if sweeps is not None:
         cfg["sweeps"] = sweeps
+        cfg["burn_in"] = sweeps // 4
     wl = Workload(name=name, seed=2000 + idx, data_seed=1000 + idx, **cfg)
     rng = np.random.default_rng(wl.data_seed)
     wl.truth = random_image(wl.height, wl.width, wl.levels, wl.shapes, wl.gradient, rng)
