@@ -24,7 +24,9 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK_VALU_TOPS = 256 * 64 * 2.4e9 / 1e12   # 256 CUs x 64 lanes x 2.4 GHz, one 32-bit op per lane per clock
+# 32-bit VALU issue rate: the FP32 vector peak of 157.3 TFLOP/s counts an FMA as two flops,
+# i.e. 256 CUs x 128 lanes x 2.4 GHz = 78.6 T lane-operations/s.
+PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_14869_amd", "csrc", "pca_kernels.hip")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c3_traffic.txt")
@@ -91,6 +93,18 @@ def cpu_baseline(wl, seconds: float):
                       f"workload, {dt:.1f} s single-threaded"}
 
 
+def copy_probe(mib: int, reps: int = 4):
+    """A plain copy of known size: its HBM byte counters calibrate those of the sweep."""
+    import torch
+    n = mib * (1 << 20)
+    a = torch.ones(n, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -100,7 +114,12 @@ def main():
     ap.add_argument("--sweeps", type=int, default=None, help="override the workload's sweep count")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of this many MiB (reference for HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
