@@ -135,12 +135,61 @@ __device__ __forceinline__ float prior_lookup(const char *ptab, const NbrPack<NW
         v = __builtin_amdgcn_sad_u8(kk, nb.lo[w], v);
         v = __builtin_amdgcn_sad_u8(kk, nb.hi[w], v);
     }
-    // byte offset 4 S = 4u - 2v + 2 sum(hi - lo)
-    const int off = (int)(4u * u) - (int)(2u * v) + nb.cb;
+    // byte offset 4 S = 4u - 2v + 2 sum(hi - lo), as one shift-add and one 24-bit mad
+    int off;
+    asm("v_lshl_add_u32 %0, %1, 2, %2\n\tv_mad_i32_i24 %0, %3, -2, %0" : "=&v"(off) : "v"(u), "v"(nb.cb), "v"(v));
     return *reinterpret_cast<const float *>(ptab + off);
 }
 
-template <int G, int NBR, int SUB, int NBLK>
+// Broadcast lane J of each group of SHARE consecutive lanes to the whole group (DPP
+// quad permutation; groups never straddle a quad).
+template <int SHARE, int J>
+__device__ __forceinline__ float group_bcast(float v)
+{
+    if constexpr (SHARE == 1) {
+        return v;
+    } else {
+        constexpr int ctrl = SHARE == 4 ? (J | (J << 2) | (J << 4) | (J << 6))
+                                        : (J | (J << 2) | ((2 + J) << 4) | ((2 + J) << 6));
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+    }
+}
+
+template <int G, int NW>
+__device__ __forceinline__ void level_update(const char *pt, const NbrPack<NW> (&nb)[G], float (&acc)[G], float D,
+                                             uint32_t kk)
+{
+#pragma unroll
+    for (int ch = 0; ch < G; ++ch) acc[ch] = __builtin_fmaf(D, prior_lookup<NW>(pt, nb[ch], kk), acc[ch]);
+}
+
+// Levels J.. of a group of SHARE consecutive levels; only the first nlev exist.
+template <int SHARE, int J, int G, int NW>
+__device__ __forceinline__ void group_levels(const char *pt, const NbrPack<NW> (&nb)[G], float (&acc)[G], float Dmine,
+                                             uint32_t &kk, int nlev)
+{
+    if constexpr (J < SHARE) {
+        if (J < nlev) {
+            level_update<G, NW>(pt, nb, acc, group_bcast<SHARE, J>(Dmine), kk);
+            kk += 0x01010101u;
+            group_levels<SHARE, J + 1, G, NW>(pt, nb, acc, Dmine, kk, nlev);
+        }
+    }
+}
+
+// All SHARE levels of a group.
+template <int SHARE, int J, int G, int NW>
+__device__ __forceinline__ void group_full(const char *pt, const NbrPack<NW> (&nb)[G], float (&acc)[G], float Dmine,
+                                           uint32_t &kk)
+{
+    if constexpr (J < SHARE) {
+        level_update<G, NW>(pt, nb, acc, group_bcast<SHARE, J>(Dmine), kk);
+        kk += 0x01010101u;
+        group_full<SHARE, J + 1, G, NW>(pt, nb, acc, Dmine, kk);
+    }
+}
+
+template <int G, int NBR, int SUB, int NBLK, int SHARE>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
 {
     constexpr int NW = NBR / 4;
@@ -222,28 +271,61 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
         acc[ch] = stay[ch];
     }
 
-    // Main pass over levels, keeping the running sum at the end of every block.
+    // Main pass over levels, keeping the running sum at the end of every block.  The
+    // SHARE lanes serving one pixel each compute the data factor of every SHARE-th level
+    // and broadcast it, so a pixel's chains share one evaluation per level.
     float part[NBLK][G];
     const int nblk = (L + SUB - 1) / SUB;
+    const int q = (int)(threadIdx.x % SHARE);
     uint32_t kk = 0u;
-    float kf = 0.0f;
+    float kq = (float)q;  // level whose data factor this lane evaluates next
+    if constexpr (SUB == 1) {
 #pragma unroll
-    for (int b = 0; b < NBLK; ++b) {
-        if (b < nblk) {
-            const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
-            for (int i = 0; i < kend; ++i) {
-                const float e = gp - kf;
-                const float D = exp2s(__builtin_fmaf(-a2, e * e, m));
+        for (int k0 = 0; k0 < NBLK; k0 += SHARE) {
+            if (k0 < L) {
+                const float e = gp - kq;
+                const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                kq += (float)SHARE;
 #pragma unroll
-                for (int ch = 0; ch < G; ++ch) {
-                    const float P = prior_lookup<NW>(pt, nb[ch], kk);
-                    acc[ch] = __builtin_fmaf(D, P, acc[ch]);
+                for (int j = 0; j < SHARE; ++j) {
+                    if (k0 + j < L) {
+                        float D;
+                        if (j == 0) D = group_bcast<SHARE, 0>(Dm);
+                        else if (j == 1) D = group_bcast<SHARE, (SHARE > 1 ? 1 : 0)>(Dm);
+                        else if (j == 2) D = group_bcast<SHARE, (SHARE > 2 ? 2 : 0)>(Dm);
+                        else D = group_bcast<SHARE, (SHARE > 3 ? 3 : 0)>(Dm);
+                        level_update<G, NW>(pt, nb, acc, D, kk);
+                        kk += 0x01010101u;
+#pragma unroll
+                        for (int ch = 0; ch < G; ++ch) part[k0 + j][ch] = acc[ch];
+                    }
                 }
-                kk += 0x01010101u;
-                kf += 1.0f;
             }
+        }
+    } else {
 #pragma unroll
-            for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
+        for (int b = 0; b < NBLK; ++b) {
+            if (b < nblk) {
+                const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
+                if (kend == SUB) {
+#pragma unroll 2
+                    for (int i = 0; i < SUB; i += SHARE) {
+                        const float e = gp - kq;
+                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        kq += (float)SHARE;
+                        group_full<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk);
+                    }
+                } else {
+                    for (int i = 0; i < kend; i += SHARE) {
+                        const float e = gp - kq;
+                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        kq += (float)SHARE;
+                        group_levels<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk, kend - i);
+                    }
+                }
+#pragma unroll
+                for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
+            }
         }
     }
 
@@ -384,15 +466,28 @@ __global__ __launch_bounds__(kBlock) void mpm_kernel(const uint32_t *hist, uint8
 
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
 
-template <int G, int NBR>
-hipError_t launch_sweep_g(const SweepArgs &a, hipStream_t s)
+template <int G, int NBR, int SHARE>
+hipError_t launch_sweep_gs(const SweepArgs &a, hipStream_t s)
 {
     const int64_t threads = (int64_t)a.H * a.W * (a.Cp / G);
     if (a.L <= 16)
-        hipLaunchKernelGGL((sweep_kernel<G, NBR, 1, 16>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((sweep_kernel<G, NBR, 1, 16, SHARE>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
     else
-        hipLaunchKernelGGL((sweep_kernel<G, NBR, 16, 16>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
+        hipLaunchKernelGGL((sweep_kernel<G, NBR, 16, 16, SHARE>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
     return hipGetLastError();
+}
+
+// Threads per pixel = Cp / G; the data factor is shared by groups of 4 or 2 of them when
+// that count allows (groups must tile the pixel's threads and align with lane quads).
+template <int G, int NBR>
+hipError_t launch_sweep_g(const SweepArgs &a, hipStream_t s)
+{
+    const int tpp = a.Cp / G;
+    if constexpr (G == 4) {
+        if (tpp % 4 == 0) return launch_sweep_gs<G, NBR, 4>(a, s);
+        if (tpp % 2 == 0) return launch_sweep_gs<G, NBR, 2>(a, s);
+    }
+    return launch_sweep_gs<G, NBR, 1>(a, s);
 }
 
 }  // namespace
