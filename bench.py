@@ -105,12 +105,97 @@ def copy_probe(mib: int, reps: int = 4):
     print(json.dumps({"copy_probe_bytes_read": n, "copy_probe_bytes_written": n, "reps": reps}), flush=True)
 
 
+def bench_batch(args):
+    """Mixed batch of 64 lattices (sides log-uniform in [128, 1024], L in {2, 16, 256},
+    4 chains, 500 sweeps): one launch per sweep for the whole batch (graph-replayed,
+    autotuned launch configuration) against one launch per lattice per sweep."""
+    import torch
+    from paper_2507_14869_amd import Batch, Sampler
+    from workloads import synth
+
+    sweeps = args.sweeps or 500
+    wls = synth.batch_mix(64, sweeps=sweeps)
+    stream = torch.cuda.current_stream()
+    problems = []
+    for w in wls:
+        kw = w.params(burn_in=sweeps // 4, tally_stride=1)
+        kw.pop("height")
+        kw.pop("width")
+        problems.append((torch.from_numpy(w.obs).cuda(), kw))
+    su = sum(w.height * w.width * w.chains for w in wls) * sweeps
+
+    def batched(cfg=None):
+        b = Batch(problems)
+        if cfg is not None:
+            b.set_config(*cfg)
+        b.sweep(sweeps)
+        outs = [b.posterior_mean(i) for i in range(len(problems))]
+        return b, outs
+
+    def per_lattice():
+        objs = []
+        for obs, kw in problems:
+            s = Sampler(obs, **kw).sweep(sweeps)
+            objs.append((s, s.posterior_mean()))
+        return objs
+
+    tuner = Batch(problems)
+    tune_ms = tuner.autotune(3)
+    cfg = tuner.config
+    tuner.close()
+    for _ in range(args.warmup):
+        b, _ = batched(cfg)
+        b.sync()
+        b.close()
+        for s, _ in per_lattice():
+            s.sync()
+            s.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    keep = [batched(cfg) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / args.steps
+    for b, _ in keep:
+        b.close()
+    t0 = time.perf_counter()
+    keep = [per_lattice() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / args.steps
+    for objs in keep:
+        for s, _ in objs:
+            s.close()
+    out = {
+        "metric": "site-updates/s",
+        "value": su / t_batch,
+        "unit": "site-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"c4: batch of {len(wls)} lattices, sides log-uniform in [128, 1024], L in {{2, 16, 256}}, "
+                        f"4 chains, {sweeps} sweeps, one launch per sweep for the batch (graph-replayed)",
+            "lattices": len(wls), "sweeps": sweeps, "site_updates_per_step": su,
+            "levels_mix": {str(L): sum(1 for w in wls if w.levels == L) for L in (2, 16, 256)},
+            "autotuned": {"chains_per_thread": cfg[0], "share": cfg[1], "tiled": cfg[2], "ms_per_sweep": tune_ms},
+        },
+        "one_launch_per_lattice": {"value": su / t_single, "ms_per_step": t_single * 1e3},
+        "speedup_vs_one_launch_per_lattice": t_single / t_batch,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3"])
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--sweeps", type=int, default=None, help="override the workload's sweep count")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -130,6 +215,10 @@ def main():
     import torch
     from paper_2507_14869_amd import Sampler
     from workloads import synth
+
+    if args.workload == "c4":
+        bench_batch(args)
+        return
 
     wl = synth.make_workload(args.workload, sweeps=args.sweeps)
     dev = torch.device("cuda:0")

@@ -122,6 +122,52 @@ int pca_destroy(pca_ctx *ctx);
 /* Message of the last error on the calling thread ("" if none). */
 const char *pca_last_error(void);
 
+/* ------------------------------------------------------------------------------------
+ * Batches.  Many independent lattices - each with its own size, level count, chains,
+ * parameters, beta schedule and seed, all with the same neighbourhood - advanced
+ * together: every sweep of the batch is ONE kernel launch covering all lattices, and
+ * the launches of a pca_batch_sweep call are captured once into a HIP graph and
+ * replayed.  Each lattice's results are bit-identical to running it alone with
+ * pca_init/pca_sweep (the draws are keyed by its own seed, chain, sweep and pixel).
+ * All lattices share one sweep index.  Conventions as above; `i` selects a lattice.
+ * ------------------------------------------------------------------------------------ */
+typedef struct pca_batch pca_batch; /* opaque, library-owned */
+
+/* Creates a batch of n >= 1 lattices from params[0..n-1] and the device observations
+ * obs_dev[0..n-1] (float32 [height][width] each, read during initialisation only).
+ * Errors: PCA_EINVAL (any invalid parameter set, NULL pointer, mixed neighbourhoods),
+ * PCA_ENOMEM, PCA_EDEVICE. */
+int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_t n, void *stream,
+                   pca_batch **out);
+
+/* Launch-configuration autotuner: times every valid configuration (chains per thread
+ * 1/2/4, lanes sharing a pixel's data factor 1/2/4, row-major or 16-pixel-wide tiled
+ * traversal) over trial_sweeps sweeps of this batch, keeps the fastest, then restores the
+ * initial states (sweep index 0, accumulators cleared).  Synchronous.  *best_ms (may be
+ * NULL) receives the winner's time per sweep.  The configuration never changes results. */
+int pca_batch_autotune(pca_batch *b, int32_t trial_sweeps, void *stream, float *best_ms);
+
+/* The launch configuration in use, or set one explicitly (PCA_EINVAL if not valid for the
+ * batch).  Setting a configuration does not change the state. */
+int pca_batch_config(const pca_batch *b, int32_t *chains_per_thread, int32_t *share, int32_t *tiled);
+int pca_batch_set_config(pca_batch *b, int32_t chains_per_thread, int32_t share, int32_t tiled, void *stream);
+
+/* Enqueues n >= 0 sweeps of every lattice (as pca_sweep).  The first call with a given n
+ * captures and instantiates a graph (a few ms); later calls replay it.  Errors: PCA_EINVAL,
+ * PCA_ESTATE (accumulator overflow), PCA_EDEVICE. */
+int pca_batch_sweep(pca_batch *b, int32_t n, void *stream);
+
+/* Per-lattice readouts and statistics, as pca_posterior_mean, pca_marginal_map,
+ * pca_get_state and pca_stats. */
+int pca_batch_posterior_mean(pca_batch *b, int32_t i, float *out_dev, void *stream);
+int pca_batch_marginal_map(pca_batch *b, int32_t i, uint8_t *out_dev, void *stream);
+int pca_batch_get_state(pca_batch *b, int32_t i, uint8_t *out_dev, void *stream);
+int pca_batch_stats(const pca_batch *b, int32_t i, int64_t *sweep, int64_t *count, int64_t *tallies);
+
+/* Waits for the batch's last stream and reports device errors; frees the batch. */
+int pca_batch_sync(pca_batch *b);
+int pca_batch_destroy(pca_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

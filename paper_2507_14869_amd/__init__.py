@@ -12,7 +12,9 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import (PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_params, pca_destroy, pca_get_state,  # noqa
                    pca_init, pca_last_error, pca_marginal_map, pca_posterior_mean, pca_set_state, pca_stats,
-                   pca_sweep, pca_sync)
+                   pca_sweep, pca_sync, pca_batch_init, pca_batch_autotune, pca_batch_config, pca_batch_set_config,
+                   pca_batch_sweep, pca_batch_posterior_mean, pca_batch_marginal_map, pca_batch_get_state,
+                   pca_batch_stats, pca_batch_sync, pca_batch_destroy)
 
 
 def _stream_handle(stream) -> int:
@@ -92,6 +94,88 @@ class Sampler:
         if getattr(self, "ctx", None):
             pca_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent lattices advanced together, one kernel launch per sweep.
+
+    ``problems`` is a sequence of (obs, params) pairs: obs a float32 [H, W] CUDA tensor and
+    params a dict of ``pca_params`` fields (``levels`` required).  All lattices share the
+    neighbourhood and the sweep index.
+    """
+
+    def __init__(self, problems, stream=None):
+        import torch
+        _lib.load()
+        self._obs = []
+        self._params = []
+        self._bufs = []
+        self.shapes = []
+        for obs, kw in problems:
+            if obs.dtype != torch.float32 or obs.dim() != 2 or not obs.is_cuda:
+                raise ValueError("obs must be float32 [H, W] CUDA tensors")
+            obs = obs.contiguous()
+            H, W = int(obs.shape[0]), int(obs.shape[1])
+            p, buf = make_params(height=H, width=W, **kw)
+            self._obs.append(obs)
+            self._params.append(p)
+            self._bufs.append(buf)
+            self.shapes.append((H, W, int(kw.get("chains", 1)), int(kw["levels"])))
+        self.device = self._obs[0].device
+        self.b = pca_batch_init(self._params, [o.data_ptr() for o in self._obs], _stream_handle(stream))
+
+    def autotune(self, trial_sweeps: int = 3, stream=None) -> float:
+        """Picks the fastest launch configuration (ms per sweep); resets the run to sweep 0."""
+        return pca_batch_autotune(self.b, trial_sweeps, _stream_handle(stream))
+
+    @property
+    def config(self):
+        return pca_batch_config(self.b)
+
+    def set_config(self, chains_per_thread: int, share: int, tiled: int, stream=None):
+        pca_batch_set_config(self.b, chains_per_thread, share, tiled, _stream_handle(stream))
+
+    def sweep(self, n: int = 1, stream=None) -> "Batch":
+        pca_batch_sweep(self.b, n, _stream_handle(stream))
+        return self
+
+    def posterior_mean(self, i: int, stream=None):
+        import torch
+        H, W, _, _ = self.shapes[i]
+        out = torch.empty((H, W), dtype=torch.float32, device=self.device)
+        pca_batch_posterior_mean(self.b, i, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def marginal_map(self, i: int, stream=None):
+        import torch
+        H, W, _, _ = self.shapes[i]
+        out = torch.empty((H, W), dtype=torch.uint8, device=self.device)
+        pca_batch_marginal_map(self.b, i, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def state(self, i: int, stream=None):
+        import torch
+        H, W, C, _ = self.shapes[i]
+        out = torch.empty((C, H, W), dtype=torch.uint8, device=self.device)
+        pca_batch_get_state(self.b, i, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def stats(self, i: int):
+        return pca_batch_stats(self.b, i)
+
+    def sync(self):
+        pca_batch_sync(self.b)
+
+    def close(self):
+        if getattr(self, "b", None):
+            pca_batch_destroy(self.b)
+            self.b = None
 
     def __del__(self):
         try:

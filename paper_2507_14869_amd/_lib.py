@@ -17,7 +17,9 @@ PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE = 0, -1, -2, -3, -4
 PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR = 0, 1
 
 EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "pca_get_state", "pca_set_state",
-            "pca_stats", "pca_sync", "pca_destroy", "pca_last_error")
+            "pca_stats", "pca_sync", "pca_destroy", "pca_batch_init", "pca_batch_autotune", "pca_batch_config",
+            "pca_batch_set_config", "pca_batch_sweep", "pca_batch_posterior_mean", "pca_batch_marginal_map",
+            "pca_batch_get_state", "pca_batch_stats", "pca_batch_sync", "pca_batch_destroy", "pca_last_error")
 
 
 class PcaError(RuntimeError):
@@ -62,6 +64,18 @@ def load():
         lib.pca_stats.argtypes = [vp, i64p, i64p, i64p]
         lib.pca_sync.argtypes = [vp]
         lib.pca_destroy.argtypes = [vp]
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        lib.pca_batch_init.argtypes = [pp, ctypes.POINTER(vp), ctypes.c_int32, vp, ctypes.POINTER(vp)]
+        lib.pca_batch_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.POINTER(ctypes.c_float)]
+        lib.pca_batch_config.argtypes = [vp, i32p, i32p, i32p]
+        lib.pca_batch_set_config.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, vp]
+        lib.pca_batch_sweep.argtypes = [vp, ctypes.c_int32, vp]
+        lib.pca_batch_posterior_mean.argtypes = [vp, ctypes.c_int32, vp, vp]
+        lib.pca_batch_marginal_map.argtypes = [vp, ctypes.c_int32, vp, vp]
+        lib.pca_batch_get_state.argtypes = [vp, ctypes.c_int32, vp, vp]
+        lib.pca_batch_stats.argtypes = [vp, ctypes.c_int32, i64p, i64p, i64p]
+        lib.pca_batch_sync.argtypes = [vp]
+        lib.pca_batch_destroy.argtypes = [vp]
         lib.pca_last_error.argtypes = []
         lib.pca_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-1]:
@@ -138,3 +152,68 @@ def pca_sync(ctx: int):
 
 def pca_destroy(ctx: int):
     _check(load().pca_destroy(ctypes.c_void_p(ctx)), "pca_destroy")
+
+
+# ------------------------------------------------------------------------------- batches
+
+def pca_batch_init(params_list, obs_ptrs, stream: int = 0) -> int:
+    """params_list: sequence of pca_params structs; obs_ptrs: device pointers, same length."""
+    n = len(params_list)
+    arr = (pca_params * n)(*params_list)
+    ptrs = (ctypes.c_void_p * n)(*[ctypes.c_void_p(int(p)) for p in obs_ptrs])
+    b = ctypes.c_void_p()
+    _check(load().pca_batch_init(arr, ptrs, n, ctypes.c_void_p(stream), ctypes.byref(b)), "pca_batch_init")
+    return b.value
+
+
+def pca_batch_autotune(b: int, trial_sweeps: int, stream: int = 0) -> float:
+    ms = ctypes.c_float()
+    _check(load().pca_batch_autotune(ctypes.c_void_p(b), int(trial_sweeps), ctypes.c_void_p(stream),
+                                     ctypes.byref(ms)), "pca_batch_autotune")
+    return ms.value
+
+
+def pca_batch_config(b: int):
+    g, s, t = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(load().pca_batch_config(ctypes.c_void_p(b), ctypes.byref(g), ctypes.byref(s), ctypes.byref(t)),
+           "pca_batch_config")
+    return g.value, s.value, t.value
+
+
+def pca_batch_set_config(b: int, chains_per_thread: int, share: int, tiled: int, stream: int = 0):
+    _check(load().pca_batch_set_config(ctypes.c_void_p(b), int(chains_per_thread), int(share), int(tiled),
+                                       ctypes.c_void_p(stream)), "pca_batch_set_config")
+
+
+def pca_batch_sweep(b: int, n: int, stream: int = 0):
+    _check(load().pca_batch_sweep(ctypes.c_void_p(b), int(n), ctypes.c_void_p(stream)), "pca_batch_sweep")
+
+
+def pca_batch_posterior_mean(b: int, i: int, out_ptr: int, stream: int = 0):
+    _check(load().pca_batch_posterior_mean(ctypes.c_void_p(b), int(i), ctypes.c_void_p(out_ptr),
+                                           ctypes.c_void_p(stream)), "pca_batch_posterior_mean")
+
+
+def pca_batch_marginal_map(b: int, i: int, out_ptr: int, stream: int = 0):
+    _check(load().pca_batch_marginal_map(ctypes.c_void_p(b), int(i), ctypes.c_void_p(out_ptr),
+                                         ctypes.c_void_p(stream)), "pca_batch_marginal_map")
+
+
+def pca_batch_get_state(b: int, i: int, out_ptr: int, stream: int = 0):
+    _check(load().pca_batch_get_state(ctypes.c_void_p(b), int(i), ctypes.c_void_p(out_ptr),
+                                      ctypes.c_void_p(stream)), "pca_batch_get_state")
+
+
+def pca_batch_stats(b: int, i: int):
+    s, c, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().pca_batch_stats(ctypes.c_void_p(b), int(i), ctypes.byref(s), ctypes.byref(c), ctypes.byref(t)),
+           "pca_batch_stats")
+    return s.value, c.value, t.value
+
+
+def pca_batch_sync(b: int):
+    _check(load().pca_batch_sync(ctypes.c_void_p(b)), "pca_batch_sync")
+
+
+def pca_batch_destroy(b: int):
+    _check(load().pca_batch_destroy(ctypes.c_void_p(b)), "pca_batch_destroy")

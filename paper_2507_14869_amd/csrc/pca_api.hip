@@ -103,6 +103,14 @@ int check_ctx(const pca_ctx *ctx)
 
 }  // namespace
 
+int pcak::validate_params(const pca_params *p) { return validate(p); }
+
+int pcak::set_error(int code, const char *message)
+{
+    g_err = message;
+    return code;
+}
+
 extern "C" {
 
 const char *pca_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,484 @@
+// C ABI of the batched sampler (declared in include/pca.h): many independent lattices of
+// different sizes, level counts and parameters advanced together, one kernel launch per
+// sweep for the whole batch, the launches of a pca_batch_sweep call replayed from a cached
+// HIP graph, and a launch-configuration autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "pca.h"
+#include "pca_internal.h"
+
+namespace {
+
+struct LaunchConfig {
+    int G = 1, share = 1, tiled = 0;
+    bool operator<(const LaunchConfig &o) const
+    {
+        return G != o.G ? G < o.G : share != o.share ? share < o.share : tiled < o.tiled;
+    }
+};
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    return pcak::set_error(code, buf);
+}
+
+int hip_fail(hipError_t e, const char *what) { return fail(PCA_EDEVICE, "%s: %s", what, hipGetErrorString(e)); }
+
+double level_scale(const pca_params &p) { return (double)(p.levels - 1) / ((double)p.vmax - (double)p.vmin); }
+
+}  // namespace
+
+struct pca_batch {
+    int device = 0;
+    int n = 0;
+    int nbr = 4;
+    std::vector<pca_params> p;
+    std::vector<pcak::ImageDesc> desc;  // host copy; pointers are device buffers
+    std::vector<int64_t> count, tallies;
+    pcak::ImageDesc *d_desc = nullptr;
+    double *d_beta = nullptr;
+    int *d_block_img = nullptr;
+    uint32_t *d_t = nullptr;
+    int64_t t = 0;
+    LaunchConfig cfg;
+    int total_blocks = 0;
+    hipStream_t cap = nullptr;  // private stream used only to capture graphs
+    std::map<int, hipGraphExec_t> graphs;
+    hipStream_t last = nullptr;
+};
+
+namespace {
+
+bool config_valid(const pca_batch *b, const LaunchConfig &c)
+{
+    for (const auto &d : b->desc) {
+        if (d.Cp % c.G != 0) return false;
+        const int tpp = d.Cp / c.G;
+        if (tpp % c.share != 0) return false;
+        if (c.tiled && (tpp > pcak::kBlock / pcak::kTileW)) return false;
+    }
+    return true;
+}
+
+std::vector<LaunchConfig> candidates(const pca_batch *b)
+{
+    std::vector<LaunchConfig> out;
+    for (int G : {4, 2, 1})
+        for (int share : {4, 2, 1})
+            for (int tiled : {0, 1}) {
+                LaunchConfig c{G, share, tiled};
+                if (config_valid(b, c)) out.push_back(c);
+            }
+    return out;
+}
+
+void drop_graphs(pca_batch *b)
+{
+    for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+}
+
+// Lays out the batched grid for a launch configuration: workgroup ranges per lattice.
+int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
+{
+    std::vector<int> block_img;
+    int base = 0;
+    for (int i = 0; i < b->n; ++i) {
+        pcak::ImageDesc &d = b->desc[i];
+        d.tpp = d.Cp / c.G;
+        d.block_base = base;
+        int blocks;
+        if (c.tiled) {
+            const int th = pcak::kBlock / d.tpp / pcak::kTileW;
+            d.tiles_w = (d.W + pcak::kTileW - 1) / pcak::kTileW;
+            blocks = d.tiles_w * ((d.H + th - 1) / th);
+        } else {
+            d.tiles_w = 0;
+            const int64_t threads = (int64_t)d.H * d.W * d.tpp;
+            blocks = (int)((threads + pcak::kBlock - 1) / pcak::kBlock);
+        }
+        if ((int64_t)base + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "batch too large for one launch");
+        block_img.insert(block_img.end(), (size_t)blocks, i);
+        base += blocks;
+    }
+    (void)hipStreamSynchronize(b->last);  // no launch of the old layout may still be running
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(b->d_block_img);
+    b->d_block_img = nullptr;
+    hipError_t e = hipMalloc(&b->d_block_img, block_img.size() * sizeof(int));
+    if (e != hipSuccess) return fail(PCA_ENOMEM, "batch: allocation failed");
+    e = hipMemcpyAsync(b->d_block_img, block_img.data(), block_img.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size() * sizeof(pcak::ImageDesc), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batch: configuration upload");
+    b->cfg = c;
+    b->total_blocks = base;
+    drop_graphs(b);
+    return PCA_OK;
+}
+
+// Initial states from the level-unit observations, zeroed accumulators, sweep index 0.
+int reset_run(pca_batch *b, const float *const *obs, hipStream_t s)
+{
+    for (int i = 0; i < b->n; ++i) {
+        const pca_params &p = b->p[i];
+        pcak::ImageDesc &d = b->desc[i];
+        const size_t N = (size_t)d.H * d.W;
+        hipError_t e = hipMemsetAsync(d.sum, 0, N * sizeof(uint32_t), s);
+        if (e == hipSuccess && d.hist) e = hipMemsetAsync(d.hist, 0, N * d.hist_words * sizeof(uint32_t), s);
+        if (e == hipSuccess) {
+            pcak::InitArgs a{};
+            a.obs = obs ? obs[i] : nullptr;
+            a.gp = const_cast<float *>(d.gp);
+            a.x = d.x0;
+            a.N = (int64_t)N;
+            a.Cp = d.Cp;
+            a.L = p.levels;
+            a.mode = p.init_mode;
+            a.vmin = (double)p.vmin;
+            a.scale = level_scale(p);
+            a.key0 = d.key0;
+            a.key1 = d.key1;
+            e = pcak::launch_init(a, s);
+        }
+        if (e != hipSuccess) return hip_fail(e, "batch: initialisation");
+        b->count[i] = 0;
+        b->tallies[i] = 0;
+    }
+    hipError_t e = hipMemsetAsync(b->d_t, 0, sizeof(uint32_t), s);
+    if (e != hipSuccess) return hip_fail(e, "batch: initialisation");
+    b->t = 0;
+    return PCA_OK;
+}
+
+void release(pca_batch *b)
+{
+    drop_graphs(b);
+    for (auto &d : b->desc) {
+        (void)hipFree(const_cast<float *>(d.gp));
+        (void)hipFree(d.x0);
+        (void)hipFree(d.x1);
+        (void)hipFree(d.sum);
+        (void)hipFree(d.hist);
+    }
+    (void)hipFree(b->d_desc);
+    (void)hipFree(b->d_beta);
+    (void)hipFree(b->d_block_img);
+    (void)hipFree(b->d_t);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
+}
+
+int check_guards(const pca_batch *b, int32_t n, std::vector<int64_t> *add_count, std::vector<int64_t> *add_tally)
+{
+    add_count->assign(b->n, 0);
+    add_tally->assign(b->n, 0);
+    for (int i = 0; i < b->n; ++i) {
+        const pca_params &p = b->p[i];
+        for (int64_t t = b->t; t < b->t + n; ++t) {
+            if (t >= p.burn_in) {
+                (*add_count)[i] += p.chains;
+                if (p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0) (*add_tally)[i] += 1;
+            }
+        }
+        if ((double)(b->count[i] + (*add_count)[i]) * (double)(p.levels - 1) > 4294967295.0)
+            return fail(PCA_ESTATE, "lattice %d: the level sum could overflow 32 bits", i);
+        if ((b->tallies[i] + (*add_tally)[i]) * (int64_t)p.chains > 65535)
+            return fail(PCA_ESTATE, "lattice %d: a histogram counter could overflow 16 bits", i);
+    }
+    if (b->t + n > 0xFFFFFFFFll) return fail(PCA_ESTATE, "sweep index overflow");
+    return PCA_OK;
+}
+
+int enqueue_eager(pca_batch *b, int32_t n, hipStream_t s)
+{
+    for (int32_t i = 0; i < n; ++i) {
+        pcak::BatchLaunch bl{b->d_desc, b->d_block_img, b->d_t, (uint32_t)i};
+        hipError_t e = pcak::launch_batch_sweep(bl, b->total_blocks, b->cfg.G, b->cfg.share, b->cfg.tiled, b->nbr, s);
+        if (e != hipSuccess) return hip_fail(e, "batch sweep");
+    }
+    hipError_t e = pcak::launch_advance(b->d_t, (uint32_t)n, s);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "batch sweep");
+}
+
+hipGraphExec_t graph_for(pca_batch *b, int32_t n, int *rc)
+{
+    auto it = b->graphs.find(n);
+    if (it != b->graphs.end()) return it->second;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        *rc = hip_fail(e, "batch: graph capture");
+        return nullptr;
+    }
+    int erc = enqueue_eager(b, n, b->cap);
+    e = hipStreamEndCapture(b->cap, &g);
+    if (erc != PCA_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        *rc = erc != PCA_OK ? erc : hip_fail(e, "batch: graph capture");
+        return nullptr;
+    }
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        *rc = hip_fail(e, "batch: graph instantiation");
+        return nullptr;
+    }
+    b->graphs[n] = ex;
+    return ex;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_t n, void *stream, pca_batch **out)
+{
+    if (!out) return fail(PCA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!params || !obs_dev || n < 1) return fail(PCA_EINVAL, "need n >= 1 parameter sets and observations");
+    for (int i = 0; i < n; ++i) {
+        int rc = pcak::validate_params(&params[i]);
+        if (rc) return rc;
+        if (!obs_dev[i]) return fail(PCA_EINVAL, "obs_dev[%d] is NULL", i);
+        if (params[i].neighbourhood != params[0].neighbourhood)
+            return fail(PCA_EINVAL, "all lattices of a batch must use the same neighbourhood");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    pca_batch *b = new pca_batch();
+    b->n = n;
+    b->nbr = params[0].neighbourhood;
+    b->last = s;
+    (void)hipGetDevice(&b->device);
+    b->p.assign(params, params + n);
+    b->count.assign(n, 0);
+    b->tallies.assign(n, 0);
+    b->desc.resize(n);
+    std::vector<double> betas;
+    std::vector<size_t> beta_off(n);
+    for (int i = 0; i < n; ++i) {
+        beta_off[i] = betas.size();
+        for (int j = 0; j < params[i].beta_len; ++j) betas.push_back((double)params[i].beta[j]);
+        b->p[i].beta = nullptr;
+    }
+    hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipMalloc(&b->d_desc, n * sizeof(pcak::ImageDesc));
+    if (e == hipSuccess) e = hipMalloc(&b->d_t, sizeof(uint32_t));
+    if (e == hipSuccess && !betas.empty()) e = hipMalloc(&b->d_beta, betas.size() * sizeof(double));
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        const pca_params &p = params[i];
+        pcak::ImageDesc &d = b->desc[i];
+        d.H = p.height;
+        d.W = p.width;
+        d.L = p.levels;
+        d.C = p.chains;
+        d.Cp = pcak::chain_slots(p.chains);
+        d.T = p.prior == PCA_PRIOR_POTTS ? 1 : (p.trunc < p.levels - 1 ? p.trunc : p.levels - 1);
+        d.hist_words = (p.levels + 1) / 2;
+        d.burn_in = p.burn_in;
+        d.tally_stride = p.tally_stride;
+        d.J = (double)p.J;
+        d.q = (double)p.q;
+        d.kappa = p.prior == PCA_PRIOR_POTTS ? 2.0 : 1.0;
+        d.sigma_s = (double)p.sigma * level_scale(p);
+        d.key0 = (uint32_t)p.seed;
+        d.key1 = (uint32_t)(p.seed >> 32);
+        d.beta_len = p.beta_len;
+        d.beta = p.beta_len > 0 ? b->d_beta + beta_off[i] : nullptr;
+        const size_t N = (size_t)d.H * d.W;
+        float *gp = nullptr;
+        e = hipMalloc(&gp, N * sizeof(float));
+        d.gp = gp;
+        if (e == hipSuccess) e = hipMalloc(&d.x0, N * d.Cp);
+        if (e == hipSuccess) e = hipMalloc(&d.x1, N * d.Cp);
+        if (e == hipSuccess) e = hipMalloc(&d.sum, N * sizeof(uint32_t));
+        if (e == hipSuccess && p.tally_stride > 0) e = hipMalloc(&d.hist, N * d.hist_words * sizeof(uint32_t));
+    }
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        release(b);
+        return fail(PCA_ENOMEM, "batch: device allocation failed");
+    }
+    if (!betas.empty()) {
+        e = hipMemcpyAsync(b->d_beta, betas.data(), betas.size() * sizeof(double), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            release(b);
+            return hip_fail(e, "batch: upload");
+        }
+    }
+    LaunchConfig c{1, 1, 0};
+    for (const auto &cand : candidates(b)) {  // largest chain group and sharing first
+        c = cand;
+        break;
+    }
+    int rc = apply_config(b, c, s);
+    if (rc == PCA_OK) rc = reset_run(b, obs_dev, s);
+    if (rc != PCA_OK) {
+        (void)hipStreamSynchronize(s);
+        release(b);
+        return rc;
+    }
+    *out = b;
+    return PCA_OK;
+}
+
+int pca_batch_autotune(pca_batch *b, int32_t trial_sweeps, void *stream, float *best_ms)
+{
+    if (!b) return fail(PCA_EINVAL, "batch is NULL");
+    if (trial_sweeps < 1) return fail(PCA_EINVAL, "trial_sweeps must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    b->last = s;
+    for (int i = 0; i < b->n; ++i)
+        if (b->p[i].init_mode != 0 && b->p[i].init_mode != 1) return fail(PCA_EINVAL, "bad init mode");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(PCA_EDEVICE, "batch autotune: event creation failed");
+    LaunchConfig best = b->cfg;
+    float best_t = 1e30f;
+    int rc = PCA_OK;
+    for (const auto &c : candidates(b)) {
+        rc = apply_config(b, c, s);
+        if (rc) break;
+        rc = enqueue_eager(b, 1, s);  // warm-up
+        if (rc) break;
+        (void)hipEventRecord(e0, s);
+        rc = enqueue_eager(b, trial_sweeps, s);
+        (void)hipEventRecord(e1, s);
+        if (rc) break;
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            rc = fail(PCA_EDEVICE, "batch autotune: timing failed");
+            break;
+        }
+        float ms = 0.0f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best_t) {
+            best_t = ms;
+            best = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc == PCA_OK) rc = apply_config(b, best, s);
+    if (rc == PCA_OK) rc = reset_run(b, nullptr, s);
+    if (rc == PCA_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(PCA_EDEVICE, "batch autotune: reset failed");
+    if (best_ms) *best_ms = best_t / (float)trial_sweeps;
+    return rc;
+}
+
+int pca_batch_config(const pca_batch *b, int32_t *chains_per_thread, int32_t *share, int32_t *tiled)
+{
+    if (!b) return fail(PCA_EINVAL, "batch is NULL");
+    if (chains_per_thread) *chains_per_thread = b->cfg.G;
+    if (share) *share = b->cfg.share;
+    if (tiled) *tiled = b->cfg.tiled;
+    return PCA_OK;
+}
+
+int pca_batch_set_config(pca_batch *b, int32_t chains_per_thread, int32_t share, int32_t tiled, void *stream)
+{
+    if (!b) return fail(PCA_EINVAL, "batch is NULL");
+    LaunchConfig c{chains_per_thread, share, tiled ? 1 : 0};
+    if ((c.G != 1 && c.G != 2 && c.G != 4) || (c.share != 1 && c.share != 2 && c.share != 4) || !config_valid(b, c))
+        return fail(PCA_EINVAL, "launch configuration not valid for this batch");
+    b->last = (hipStream_t)stream;
+    return apply_config(b, c, (hipStream_t)stream);
+}
+
+int pca_batch_sweep(pca_batch *b, int32_t n, void *stream)
+{
+    if (!b) return fail(PCA_EINVAL, "batch is NULL");
+    if (n < 0) return fail(PCA_EINVAL, "n must be >= 0");
+    if (n == 0) return PCA_OK;
+    std::vector<int64_t> add_count, add_tally;
+    int rc = check_guards(b, n, &add_count, &add_tally);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    b->last = s;
+    hipGraphExec_t ex = graph_for(b, n, &rc);
+    if (!ex) return rc;
+    hipError_t e = hipGraphLaunch(ex, s);
+    if (e != hipSuccess) return hip_fail(e, "batch sweep: graph launch");
+    b->t += n;
+    for (int i = 0; i < b->n; ++i) {
+        b->count[i] += add_count[i];
+        b->tallies[i] += add_tally[i];
+    }
+    return PCA_OK;
+}
+
+int pca_batch_posterior_mean(pca_batch *b, int32_t i, float *out_dev, void *stream)
+{
+    if (!b || i < 0 || i >= b->n || !out_dev) return fail(PCA_EINVAL, "bad batch, index or output");
+    if (b->count[i] <= 0) return fail(PCA_ESTATE, "no accumulated sweeps");
+    const pca_params &p = b->p[i];
+    const pcak::ImageDesc &d = b->desc[i];
+    const double delta = ((double)p.vmax - (double)p.vmin) / (double)(p.levels - 1);
+    b->last = (hipStream_t)stream;
+    hipError_t e = pcak::launch_mean(d.sum, out_dev, (int64_t)d.H * d.W, b->count[i], (double)p.vmin, delta,
+                                     (hipStream_t)stream);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "batch posterior mean");
+}
+
+int pca_batch_marginal_map(pca_batch *b, int32_t i, uint8_t *out_dev, void *stream)
+{
+    if (!b || i < 0 || i >= b->n || !out_dev) return fail(PCA_EINVAL, "bad batch, index or output");
+    const pcak::ImageDesc &d = b->desc[i];
+    if (!d.hist) return fail(PCA_ESTATE, "histogram disabled (tally_stride = 0)");
+    if (b->tallies[i] <= 0) return fail(PCA_ESTATE, "no tally sweeps yet");
+    b->last = (hipStream_t)stream;
+    hipError_t e = pcak::launch_mpm(d.hist, out_dev, (int64_t)d.H * d.W, d.L, d.hist_words, (hipStream_t)stream);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "batch marginal map");
+}
+
+int pca_batch_get_state(pca_batch *b, int32_t i, uint8_t *out_dev, void *stream)
+{
+    if (!b || i < 0 || i >= b->n || !out_dev) return fail(PCA_EINVAL, "bad batch, index or output");
+    const pcak::ImageDesc &d = b->desc[i];
+    b->last = (hipStream_t)stream;
+    hipError_t e = pcak::launch_get_state((b->t & 1) ? d.x1 : d.x0, out_dev, (int64_t)d.H * d.W, d.C, d.Cp,
+                                          (hipStream_t)stream);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "batch get state");
+}
+
+int pca_batch_stats(const pca_batch *b, int32_t i, int64_t *sweep, int64_t *count, int64_t *tallies)
+{
+    if (!b || i < 0 || i >= b->n) return fail(PCA_EINVAL, "bad batch or index");
+    if (sweep) *sweep = b->t;
+    if (count) *count = b->count[i];
+    if (tallies) *tallies = b->tallies[i];
+    return PCA_OK;
+}
+
+int pca_batch_sync(pca_batch *b)
+{
+    if (!b) return fail(PCA_EINVAL, "batch is NULL");
+    hipError_t e = hipStreamSynchronize(b->last);
+    if (e == hipSuccess) e = hipGetLastError();
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_batch_sync");
+}
+
+int pca_batch_destroy(pca_batch *b)
+{
+    if (!b) return PCA_OK;
+    hipError_t e = hipStreamSynchronize(b->last);
+    release(b);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_batch_destroy");
+}
+
+}  // extern "C"

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "pca.h"
+
 namespace pcak {
 
 constexpr int kBlock = 256;                 // threads per workgroup (4 wave64)
@@ -29,7 +31,7 @@ struct SweepArgs {
 };
 
 struct InitArgs {
-    const float *obs;  // [N] value units
+    const float *obs;  // [N] value units, or nullptr to re-initialise from gp
     float *gp;         // [N] level units
     uint8_t *x;        // [N][Cp]
     int64_t N;
@@ -40,6 +42,40 @@ struct InitArgs {
 
 // Chains handled by one thread: 4 (one Philox call feeds four chains) unless fewer exist.
 inline int chain_group(int chains) { return chains >= 3 ? 4 : chains; }
+// Chain slots in the interleaved state: chains rounded up to a multiple of 4 (1 or 2 stay).
+inline int chain_slots(int chains) { return chains <= 2 ? chains : (chains + 3) / 4 * 4; }
+
+// One lattice of a batch, resident in device memory; read by every workgroup of it.
+struct ImageDesc {
+    const float *gp;
+    uint8_t *x0, *x1;     // state buffers: sweep t reads x[t & 1] and writes the other
+    uint32_t *sum, *hist;
+    const double *beta;   // per-sweep beta (device), beta_len entries; none => 1
+    int beta_len;
+    int H, W, L, C, Cp, T, hist_words, burn_in, tally_stride;
+    double J, q, kappa, sigma_s;
+    uint32_t key0, key1;
+    int tpp;              // threads per pixel (Cp / G) in the launch configuration in use
+    int block_base;       // first workgroup of this lattice in the batched grid
+    int tiles_w;          // tiled traversal: tiles per tile row
+};
+
+struct BatchLaunch {
+    const ImageDesc *imgs;
+    const int *block_img;   // workgroup -> lattice
+    const uint32_t *t_dev;  // sweep index of the batch before this graph replay
+    uint32_t toff;          // sweep offset of this launch within the replay
+};
+
+constexpr int kTileW = 16;  // tiled traversal: tiles 16 pixels wide, kBlock / tpp pixels each
+
+hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr,
+                              hipStream_t s);
+hipError_t launch_advance(uint32_t *t_dev, uint32_t n, hipStream_t s);
+
+// Shared by the single-lattice and batch entry points (pca_api.hip).
+int validate_params(const pca_params *p);     // PCA_OK or PCA_EINVAL with the error message set
+int set_error(int code, const char *message);  // records the calling thread's last error, returns code
 
 hipError_t launch_init(const InitArgs &a, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs &a, int G, int nbr, hipStream_t s);

@@ -189,29 +189,35 @@ __device__ __forceinline__ void group_full(const char *pt, const NbrPack<NW> (&n
     }
 }
 
-template <int G, int NBR, int SUB, int NBLK, int SHARE>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
-{
-    constexpr int NW = NBR / 4;
-    __shared__ float ptab[kMaxNeighbourStat + 1];
+// Per-sweep scalars shared by a workgroup, and the prior factor table P(S), S = 0..nbr*T,
+// in LDS.  Every thread of the workgroup must call this (it ends with a barrier).
+struct SweepConsts {
+    float R, a2;
+};
 
-    // Per-sweep constants, same for every thread.
+__device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nbr, float *ptab)
+{
     const float c2 = (float)(((a.beta * a.J) * a.kappa) * kLog2e);
     const float q2 = (float)((a.beta * a.q) * kLog2e);
-    const float R = exp2s(q2) - 1.0f;
-    const float a2 = (float)(kLog2e / ((2.0 * a.sigma_s) * a.sigma_s));
-    const int nP = NBR * a.T + 1;
-    for (int s = threadIdx.x; s < nP; s += kBlock) ptab[s] = exp2s(-(c2 * (float)s));
+    SweepConsts k;
+    k.R = exp2s(q2) - 1.0f;
+    k.a2 = (float)(kLog2e / ((2.0 * a.sigma_s) * a.sigma_s));
+    const int nP = nbr * a.T + 1;
+    for (int s = threadIdx.x; s < nP; s += blockDim.x) ptab[s] = exp2s(-(c2 * (float)s));
     __syncthreads();
+    return k;
+}
 
+// One thread's site updates: pixel (r, c) = pix, chains grp*G .. grp*G+G-1.  `q` is the
+// thread's position in its group of SHARE lanes serving the same pixel.
+template <int G, int NBR, int SUB, int NBLK, int SHARE>
+__device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab, SweepConsts kc, int pix, int r,
+                                           int c, int grp, int q)
+{
+    constexpr int NW = NBR / 4;
+    const float R = kc.R;
+    const float a2 = kc.a2;
     const int tpp = a.Cp / G;
-    const int64_t N = (int64_t)a.H * a.W;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= N * tpp) return;
-    const int pix = (int)(gid / tpp);
-    const int grp = (int)(gid - (int64_t)pix * tpp);
-    const int r = pix / a.W;
-    const int c = pix - r * a.W;
     const int cofs = grp * G;
     const int L = a.L;
 
@@ -276,7 +282,6 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
     // and broadcast it, so a pixel's chains share one evaluation per level.
     float part[NBLK][G];
     const int nblk = (L + SUB - 1) / SUB;
-    const int q = (int)(threadIdx.x % SHARE);
     uint32_t kk = 0u;
     float kq = (float)q;  // level whose data factor this lane evaluates next
     if constexpr (SUB == 1) {
@@ -395,14 +400,35 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
     }
 }
 
+// One sweep of one lattice: thread gid = pixel * (Cp/G) + chain group, row-major pixels.
+template <int G, int NBR, int SUB, int NBLK, int SHARE>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
+{
+    __shared__ float ptab[kMaxNeighbourStat + 1];
+    const SweepConsts kc = sweep_prologue(a, NBR, ptab);
+    const int tpp = a.Cp / G;
+    const int64_t N = (int64_t)a.H * a.W;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (gid >= N * tpp) return;
+    const int pix = (int)(gid / tpp);
+    const int grp = (int)(gid - (int64_t)pix * tpp);
+    const int r = pix / a.W;
+    sweep_site<G, NBR, SUB, NBLK, SHARE>(a, ptab, kc, pix, r, pix - r * a.W, grp, (int)(threadIdx.x % SHARE));
+}
+
 // ---------------------------------------------------------------- init and readouts
 
 __global__ __launch_bounds__(kBlock) void init_kernel(InitArgs a)
 {
     const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (pix >= a.N) return;
-    const float gp = (float)(((double)a.obs[pix] - a.vmin) * a.scale);
-    a.gp[pix] = gp;
+    float gp;
+    if (a.obs) {
+        gp = (float)(((double)a.obs[pix] - a.vmin) * a.scale);
+        a.gp[pix] = gp;
+    } else {
+        gp = a.gp[pix];
+    }
     float kh = __builtin_rintf(gp);
     kh = kh < 0.0f ? 0.0f : kh;
     kh = kh > (float)(a.L - 1) ? (float)(a.L - 1) : kh;
@@ -464,7 +490,91 @@ __global__ __launch_bounds__(kBlock) void mpm_kernel(const uint32_t *hist, uint8
     out[pix] = (uint8_t)best;
 }
 
+// ---------------------------------------------------------------- batched sweep
+
+// One sweep of every lattice of a batch in one launch.  Each workgroup belongs to one
+// lattice (its descriptor is read once, uniformly); lattices may differ in size, level
+// count, chains, parameters and seed.  The sweep index comes from device memory so a
+// captured graph of n launches can be replayed for the next n sweeps.
+template <int G, int SHARE, int TILED, int NBR>
+__global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
+{
+    __shared__ float ptab[kMaxNeighbourStat + 1];
+    const int img = b.block_img[blockIdx.x];
+    const ImageDesc &d = b.imgs[img];
+    const uint32_t t = *b.t_dev + b.toff;
+    SweepArgs a;
+    a.gp = d.gp;
+    a.xin = (t & 1u) ? d.x1 : d.x0;
+    a.xout = (t & 1u) ? d.x0 : d.x1;
+    const bool acc = (int64_t)t >= d.burn_in;
+    const bool tally = acc && d.tally_stride > 0 && ((int64_t)t - d.burn_in) % d.tally_stride == 0;
+    a.sum = acc ? d.sum : nullptr;
+    a.hist = tally ? d.hist : nullptr;
+    a.H = d.H;
+    a.W = d.W;
+    a.L = d.L;
+    a.C = d.C;
+    a.Cp = d.Cp;
+    a.T = d.T;
+    a.hist_words = d.hist_words;
+    a.beta = d.beta_len == 0 ? 1.0 : d.beta[(int)t < d.beta_len ? (int)t : d.beta_len - 1];
+    a.J = d.J;
+    a.q = d.q;
+    a.kappa = d.kappa;
+    a.sigma_s = d.sigma_s;
+    a.key0 = d.key0;
+    a.key1 = d.key1;
+    a.t = t;
+    const SweepConsts kc = sweep_prologue(a, NBR, ptab);
+
+    const int tpp = d.tpp;
+    const int local = (int)blockIdx.x - d.block_base;
+    int pix, r, c, grp;
+    if constexpr (TILED == 0) {
+        const int64_t gid = (int64_t)local * kBlock + threadIdx.x;
+        if (gid >= (int64_t)d.H * d.W * tpp) return;
+        pix = (int)(gid / tpp);
+        grp = (int)(gid - (int64_t)pix * tpp);
+        r = pix / d.W;
+        c = pix - r * d.W;
+    } else {
+        const int th = kBlock / tpp / kTileW;  // tile height in pixels
+        const int tr = local / d.tiles_w, tc = local - (local / d.tiles_w) * d.tiles_w;
+        const int lp = (int)threadIdx.x / tpp;
+        grp = (int)threadIdx.x - lp * tpp;
+        r = tr * th + lp / kTileW;
+        c = tc * kTileW + lp % kTileW;
+        if (r >= d.H || c >= d.W) return;
+        pix = r * d.W + c;
+    }
+    const int q = (int)(threadIdx.x % SHARE);
+    if (a.L <= 16) sweep_site<G, NBR, 1, 16, SHARE>(a, ptab, kc, pix, r, c, grp, q);
+    else sweep_site<G, NBR, 16, 16, SHARE>(a, ptab, kc, pix, r, c, grp, q);
+}
+
+__global__ void advance_kernel(uint32_t *t_dev, uint32_t n)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *t_dev += n;
+}
+
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+template <int G, int SHARE, int TILED>
+hipError_t launch_batch_gst(const BatchLaunch &b, int blocks, int nbr, hipStream_t s)
+{
+    if (nbr == 8)
+        hipLaunchKernelGGL((batch_sweep_kernel<G, SHARE, TILED, 8>), dim3(blocks), dim3(kBlock), 0, s, b);
+    else
+        hipLaunchKernelGGL((batch_sweep_kernel<G, SHARE, TILED, 4>), dim3(blocks), dim3(kBlock), 0, s, b);
+    return hipGetLastError();
+}
+
+template <int G, int SHARE>
+hipError_t launch_batch_gs(const BatchLaunch &b, int blocks, int tiled, int nbr, hipStream_t s)
+{
+    return tiled ? launch_batch_gst<G, SHARE, 1>(b, blocks, nbr, s) : launch_batch_gst<G, SHARE, 0>(b, blocks, nbr, s);
+}
 
 template <int G, int NBR, int SHARE>
 hipError_t launch_sweep_gs(const SweepArgs &a, hipStream_t s)
@@ -502,6 +612,29 @@ hipError_t launch_sweep(const SweepArgs &a, int G, int nbr, hipStream_t s)
     if (G == 4) return launch_sweep_g<4, 8>(a, s);
     if (G == 2) return launch_sweep_g<2, 8>(a, s);
     return launch_sweep_g<1, 8>(a, s);
+}
+
+hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr,
+                              hipStream_t s)
+{
+    if (G == 4) {
+        if (share == 4) return launch_batch_gs<4, 4>(b, total_blocks, tiled, nbr, s);
+        if (share == 2) return launch_batch_gs<4, 2>(b, total_blocks, tiled, nbr, s);
+        return launch_batch_gs<4, 1>(b, total_blocks, tiled, nbr, s);
+    }
+    if (G == 2) {
+        if (share == 2) return launch_batch_gs<2, 2>(b, total_blocks, tiled, nbr, s);
+        return launch_batch_gs<2, 1>(b, total_blocks, tiled, nbr, s);
+    }
+    if (share == 4) return launch_batch_gs<1, 4>(b, total_blocks, tiled, nbr, s);
+    if (share == 2) return launch_batch_gs<1, 2>(b, total_blocks, tiled, nbr, s);
+    return launch_batch_gs<1, 1>(b, total_blocks, tiled, nbr, s);
+}
+
+hipError_t launch_advance(uint32_t *t_dev, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, t_dev, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const InitArgs &a, hipStream_t s)

@@ -1,0 +1,119 @@
+"""Batched sweeps (one launch per sweep over many lattices, graph-replayed) against the
+single-lattice path and the CPU oracle: every lattice must come out bit-identical to
+running it alone, for every launch configuration, across repeated graph replays with
+eager work and synchronisation in between."""
+import numpy as np
+import pytest
+
+try:  # import at collection so the first GPU test's time limit does not include it
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+from tests.gpu_util import gpu_sampler, oracle_run, torch_cuda
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(H, W, L, C, seed, **over):
+    rng = np.random.default_rng(seed)
+    truth = synth.random_image(H, W, L, max(2, H * W // 300), L > 2, rng)
+    sigma = float(rng.uniform(0.1, 0.3) * L)
+    obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), sigma, rng)
+    fam = {2: (0, 1, 0.8)}.get(L, (1, 4 if L <= 16 else 32, 0.4 if L <= 16 else 0.05))
+    kw = dict(levels=L, chains=C, prior=fam[0], trunc=fam[1], J=float(fam[2] * rng.uniform(0.5, 1.5)),
+              q=float(rng.uniform(1.0, 2.0)), sigma=sigma, vmin=0.0, vmax=float(L - 1), seed=int(seed) * 7919 + 1,
+              burn_in=2, tally_stride=1, beta=[1.0, 1.25, 1.5])
+    kw.update(over)
+    return obs, kw
+
+
+def _batch(problems):
+    torch = torch_cuda()
+    from paper_2507_14869_amd import Batch
+    return Batch([(torch.from_numpy(o).cuda(), kw) for o, kw in problems])
+
+
+def _alone(obs, kw, sweeps):
+    return gpu_sampler(obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(sweeps)
+
+
+MIXED = [(37, 53, 256, 4, 1), (64, 64, 2, 4, 2), (17, 200, 16, 4, 3), (1, 1, 16, 4, 4), (90, 33, 256, 4, 5),
+         (128, 96, 2, 4, 6), (5, 7, 33, 4, 7)]
+MIXED_CHAINS = [(30, 31, 16, 1, 11), (22, 40, 256, 2, 12), (19, 19, 2, 3, 13), (40, 12, 33, 5, 14),
+                (16, 16, 7, 8, 15)]
+
+
+@pytest.mark.parametrize("config", [(4, 1, 0), (4, 1, 1), (2, 2, 0), (2, 1, 1), (1, 4, 0), (1, 4, 1), (1, 2, 0),
+                                    (1, 1, 1)])
+def test_batch_matches_lattices_run_alone(config):
+    problems = [_problem(*spec[:4], seed=spec[4]) for spec in MIXED]
+    b = _batch(problems)
+    b.set_config(*config)
+    assert b.config == config
+    done = 0
+    for rep in range(3):  # three replays of the same captured graph, eager work in between
+        b.sweep(4)
+        done += 4
+        for i, (obs, kw) in enumerate(problems):
+            ref = _alone(obs, kw, done)
+            assert np.array_equal(b.state(i).cpu().numpy(), ref.state().cpu().numpy()), (config, rep, i)
+            assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean().cpu().numpy())
+            assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map().cpu().numpy())
+            assert b.stats(i) == ref.stats()
+            ref.close()
+        b.sync()
+    b.close()
+
+
+def test_batch_with_mixed_chain_counts():
+    problems = [_problem(*spec[:4], seed=spec[4]) for spec in MIXED_CHAINS]
+    b = _batch(problems)
+    assert b.config[0] == 1  # only one chain per thread divides every chain count here
+    b.sweep(5).sweep(5)
+    for i, (obs, kw) in enumerate(problems):
+        ref = _alone(obs, kw, 10)
+        assert np.array_equal(b.state(i).cpu().numpy(), ref.state().cpu().numpy()), i
+        assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean().cpu().numpy())
+    with pytest.raises(Exception):
+        b.set_config(4, 1, 0)
+
+
+def test_batch_autotune_restores_initial_state_and_keeps_results(orc):
+    problems = [_problem(*spec[:4], seed=spec[4]) for spec in MIXED[:4]]
+    b = _batch(problems)
+    ms = b.autotune(2)
+    assert ms > 0
+    assert b.stats(0) == (0, 0, 0)
+    b.sweep(6)
+    for i, (obs, kw) in enumerate(problems):
+        ref = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(6)
+        assert np.array_equal(b.state(i).cpu().numpy(), ref.state), i
+        assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean())
+        assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map())
+
+
+def test_batch_rejects_mixed_neighbourhoods_and_bad_configs():
+    from paper_2507_14869_amd import PcaError
+    p1 = _problem(16, 16, 16, 4, 1)
+    p2 = _problem(16, 16, 16, 4, 2, neighbourhood=8)
+    with pytest.raises(PcaError):
+        _batch([p1, p2])
+    b = _batch([p1])
+    with pytest.raises(PcaError):
+        b.set_config(3, 1, 0)
+    with pytest.raises(PcaError):
+        b.sweep(-1)
+    with pytest.raises(PcaError):
+        b.posterior_mean(0)  # nothing accumulated yet (burn-in 2)
+    b.close()
+
+
+def test_batch_eight_neighbour():
+    problems = [_problem(24, 29, L, 4, s, neighbourhood=8, prior=0, trunc=1) for s, L in ((21, 5), (22, 9), (23, 33))]
+    b = _batch(problems)
+    b.sweep(7)
+    for i, (obs, kw) in enumerate(problems):
+        ref = _alone(obs, kw, 7)
+        assert np.array_equal(b.state(i).cpu().numpy(), ref.state().cpu().numpy()), i
