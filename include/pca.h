@@ -168,6 +168,60 @@ int pca_batch_stats(const pca_batch *b, int32_t i, int64_t *sweep, int64_t *coun
 int pca_batch_sync(pca_batch *b);
 int pca_batch_destroy(pca_batch *b);
 
+/* ------------------------------------------------------------------------------------
+ * Request server: continuous batching of denoising requests.  Submitted requests wait in
+ * a first-come-first-served queue until their device footprint fits the memory budget
+ * and an active slot is free.  Each pca_server_step admits what fits, then gives every
+ * admitted request at least one sweep and spends the rest of a GPU-time budget (step_ms,
+ * from a cost model refined with every measured step) half on the requests with the least
+ * remaining work and half on the oldest ones; the sweeps run as batched kernel launches,
+ * launch i covering every
+ * request still advancing at i, each at its own sweep index.  Finished requests are read
+ * out to host memory and their device memory released at once, so queued requests can
+ * join at the next step.  A request's results are bit-identical to running it alone with
+ * pca_init/pca_sweep.  The server is not thread-safe.
+ * ------------------------------------------------------------------------------------ */
+typedef struct pca_server pca_server; /* opaque, library-owned */
+
+/* hbm_budget_bytes: device memory the admitted requests may hold together; max_active:
+ * 1..4096 concurrently admitted requests; sweeps_per_step >= 1: most sweeps one request
+ * takes in one step; step_ms > 0: GPU time a step aims at.  Errors: PCA_EINVAL,
+ * PCA_ENOMEM. */
+int pca_server_create(uint64_t hbm_budget_bytes, int32_t max_active, int32_t sweeps_per_step, float step_ms,
+                      pca_server **out);
+
+/* Queues a request: parameters as for pca_init, the observation as a HOST float32
+ * [height][width] array (copied), and the number of sweeps to run.  *request_id receives
+ * a positive id.  Errors: PCA_EINVAL (invalid parameters, a footprint above the whole
+ * budget, or accumulators that could overflow). */
+int pca_server_submit(pca_server *sv, const pca_params *params, const float *obs_host, int32_t sweeps,
+                      int64_t *request_id);
+
+/* One scheduling step on `stream` (synchronous: returns when the step's work is done).
+ * *n_completed (may be NULL) receives the number of requests finished in this step. */
+int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed);
+
+/* Ids of requests finished since the last call (at most `capacity`, oldest first). */
+int pca_server_completed(pca_server *sv, int64_t *ids, int32_t capacity, int32_t *n);
+
+/* status: 0 queued, 1 active, 2 finished; *sweep: sweeps done so far. */
+int pca_server_status(const pca_server *sv, int64_t id, int32_t *status, int64_t *sweep);
+
+/* Copies a finished request's posterior mean (float32 [H][W], value units), marginal mode
+ * (uint8 [H][W]) and last states (uint8 [chains][H][W]) to host arrays; any may be NULL.
+ * Errors: PCA_ESTATE if the request has not finished or the output does not exist. */
+int pca_server_result(pca_server *sv, int64_t id, float *mean_host, uint8_t *mpm_host, uint8_t *state_host);
+
+/* Forgets a finished request and its host results. */
+int pca_server_release(pca_server *sv, int64_t id);
+
+/* Queue length, admitted requests, device bytes they hold, steps and sweeps launched. */
+int pca_server_stats(const pca_server *sv, int32_t *queued, int32_t *active, uint64_t *used_bytes, int64_t *steps,
+                     int64_t *sweeps_launched);
+
+/* Waits for the last stream used and frees everything.  NULL is a no-op. */
+int pca_server_destroy(pca_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

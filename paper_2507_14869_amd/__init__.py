@@ -14,7 +14,9 @@ from ._lib import (PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_param
                    pca_init, pca_last_error, pca_marginal_map, pca_posterior_mean, pca_set_state, pca_stats,
                    pca_sweep, pca_sync, pca_batch_init, pca_batch_autotune, pca_batch_config, pca_batch_set_config,
                    pca_batch_sweep, pca_batch_posterior_mean, pca_batch_marginal_map, pca_batch_get_state,
-                   pca_batch_stats, pca_batch_sync, pca_batch_destroy)
+                   pca_batch_stats, pca_batch_sync, pca_batch_destroy, pca_server_create, pca_server_submit,
+                   pca_server_step, pca_server_completed, pca_server_status, pca_server_result, pca_server_release,
+                   pca_server_stats, pca_server_destroy)
 
 
 def _stream_handle(stream) -> int:
@@ -176,6 +178,69 @@ class Batch:
         if getattr(self, "b", None):
             pca_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server (see ``pca_server_*`` in include/pca.h).
+
+    ``submit(obs, sweeps, **params)`` takes a host float32 [H, W] numpy array; ``step()``
+    admits what fits the device-memory budget and advances every admitted request (at least
+    one sweep each, the rest of a ``step_ms`` GPU-time budget to the requests with the least
+    remaining work); ``result(id)`` returns (mean, mode, states) as numpy arrays.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, max_active: int = 256, sweeps_per_step: int = 300,
+                 step_ms: float = 20.0):
+        _lib.load()
+        self.sv = pca_server_create(hbm_budget_bytes, max_active, sweeps_per_step, step_ms)
+        self._shapes = {}
+
+    def submit(self, obs, sweeps: int, **kw) -> int:
+        import numpy as np
+        obs = np.ascontiguousarray(obs, dtype=np.float32)
+        H, W = obs.shape
+        p, buf = make_params(height=H, width=W, **kw)
+        rid = pca_server_submit(self.sv, p, obs.ctypes.data, sweeps)
+        self._shapes[rid] = (H, W, int(kw.get("chains", 1)), int(kw.get("tally_stride", 0)) > 0)
+        return rid
+
+    def step(self, stream=None) -> int:
+        return pca_server_step(self.sv, _stream_handle(stream))
+
+    def completed(self):
+        return pca_server_completed(self.sv)
+
+    def status(self, rid: int):
+        return pca_server_status(self.sv, rid)
+
+    def result(self, rid: int):
+        import numpy as np
+        H, W, C, has_mpm = self._shapes[rid]
+        mean = np.empty((H, W), np.float32)
+        state = np.empty((C, H, W), np.uint8)
+        mpm = np.empty((H, W), np.uint8) if has_mpm else None
+        pca_server_result(self.sv, rid, mean.ctypes.data, mpm.ctypes.data if mpm is not None else 0,
+                          state.ctypes.data)
+        return mean, mpm, state
+
+    def release(self, rid: int):
+        pca_server_release(self.sv, rid)
+        self._shapes.pop(rid, None)
+
+    def stats(self):
+        """(queued, active, device bytes held, steps, sweeps launched)."""
+        return pca_server_stats(self.sv)
+
+    def close(self):
+        if getattr(self, "sv", None):
+            pca_server_destroy(self.sv)
+            self.sv = None
 
     def __del__(self):
         try:

@@ -19,7 +19,9 @@ PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR = 0, 1
 EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "pca_get_state", "pca_set_state",
             "pca_stats", "pca_sync", "pca_destroy", "pca_batch_init", "pca_batch_autotune", "pca_batch_config",
             "pca_batch_set_config", "pca_batch_sweep", "pca_batch_posterior_mean", "pca_batch_marginal_map",
-            "pca_batch_get_state", "pca_batch_stats", "pca_batch_sync", "pca_batch_destroy", "pca_last_error")
+            "pca_batch_get_state", "pca_batch_stats", "pca_batch_sync", "pca_batch_destroy", "pca_server_create",
+            "pca_server_submit", "pca_server_step", "pca_server_completed", "pca_server_status", "pca_server_result",
+            "pca_server_release", "pca_server_stats", "pca_server_destroy", "pca_last_error")
 
 
 class PcaError(RuntimeError):
@@ -76,6 +78,17 @@ def load():
         lib.pca_batch_stats.argtypes = [vp, ctypes.c_int32, i64p, i64p, i64p]
         lib.pca_batch_sync.argtypes = [vp]
         lib.pca_batch_destroy.argtypes = [vp]
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        lib.pca_server_create.argtypes = [ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                                          ctypes.POINTER(vp)]
+        lib.pca_server_submit.argtypes = [vp, pp, vp, ctypes.c_int32, i64p]
+        lib.pca_server_step.argtypes = [vp, vp, i32p]
+        lib.pca_server_completed.argtypes = [vp, i64p, ctypes.c_int32, i32p]
+        lib.pca_server_status.argtypes = [vp, ctypes.c_int64, i32p, i64p]
+        lib.pca_server_result.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
+        lib.pca_server_release.argtypes = [vp, ctypes.c_int64]
+        lib.pca_server_stats.argtypes = [vp, i32p, i32p, u64p, i64p, i64p]
+        lib.pca_server_destroy.argtypes = [vp]
         lib.pca_last_error.argtypes = []
         lib.pca_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-1]:
@@ -217,3 +230,60 @@ def pca_batch_sync(b: int):
 
 def pca_batch_destroy(b: int):
     _check(load().pca_batch_destroy(ctypes.c_void_p(b)), "pca_batch_destroy")
+
+
+# -------------------------------------------------------------------------------- server
+
+def pca_server_create(hbm_budget_bytes: int, max_active: int, sweeps_per_step: int, step_ms: float = 20.0) -> int:
+    sv = ctypes.c_void_p()
+    _check(load().pca_server_create(int(hbm_budget_bytes), int(max_active), int(sweeps_per_step), float(step_ms),
+                                    ctypes.byref(sv)), "pca_server_create")
+    return sv.value
+
+
+def pca_server_submit(sv: int, params: pca_params, obs_host_ptr: int, sweeps: int) -> int:
+    rid = ctypes.c_int64()
+    _check(load().pca_server_submit(ctypes.c_void_p(sv), ctypes.byref(params), ctypes.c_void_p(obs_host_ptr),
+                                    int(sweeps), ctypes.byref(rid)), "pca_server_submit")
+    return rid.value
+
+
+def pca_server_step(sv: int, stream: int = 0) -> int:
+    n = ctypes.c_int32()
+    _check(load().pca_server_step(ctypes.c_void_p(sv), ctypes.c_void_p(stream), ctypes.byref(n)), "pca_server_step")
+    return n.value
+
+
+def pca_server_completed(sv: int, capacity: int = 4096):
+    ids = (ctypes.c_int64 * max(1, capacity))()
+    n = ctypes.c_int32()
+    _check(load().pca_server_completed(ctypes.c_void_p(sv), ids, int(capacity), ctypes.byref(n)),
+           "pca_server_completed")
+    return [ids[i] for i in range(n.value)]
+
+
+def pca_server_status(sv: int, rid: int):
+    st, sw = ctypes.c_int32(), ctypes.c_int64()
+    _check(load().pca_server_status(ctypes.c_void_p(sv), int(rid), ctypes.byref(st), ctypes.byref(sw)),
+           "pca_server_status")
+    return st.value, sw.value
+
+
+def pca_server_result(sv: int, rid: int, mean_ptr: int, mpm_ptr: int, state_ptr: int):
+    _check(load().pca_server_result(ctypes.c_void_p(sv), int(rid), ctypes.c_void_p(mean_ptr), ctypes.c_void_p(mpm_ptr),
+                                    ctypes.c_void_p(state_ptr)), "pca_server_result")
+
+
+def pca_server_release(sv: int, rid: int):
+    _check(load().pca_server_release(ctypes.c_void_p(sv), int(rid)), "pca_server_release")
+
+
+def pca_server_stats(sv: int):
+    q, a, u, st, sw = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_uint64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(load().pca_server_stats(ctypes.c_void_p(sv), ctypes.byref(q), ctypes.byref(a), ctypes.byref(u),
+                                   ctypes.byref(st), ctypes.byref(sw)), "pca_server_stats")
+    return q.value, a.value, u.value, st.value, sw.value
+
+
+def pca_server_destroy(sv: int):
+    _check(load().pca_server_destroy(ctypes.c_void_p(sv)), "pca_server_destroy")

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpca.so")
-SOURCES = ["pca_kernels.hip", "pca_api.hip", "pca_batch.hip"]
+SOURCES = ["pca_kernels.hip", "pca_api.hip", "pca_batch.hip", "pca_serve.hip"]
 
 
 def hipcc() -> str:

@@ -51,7 +51,6 @@ struct pca_batch {
     pcak::ImageDesc *d_desc = nullptr;
     double *d_beta = nullptr;
     int *d_block_img = nullptr;
-    uint32_t *d_t = nullptr;
     int64_t t = 0;
     LaunchConfig cfg;
     int total_blocks = 0;
@@ -116,6 +115,10 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
     }
     (void)hipStreamSynchronize(b->last);  // no launch of the old layout may still be running
     (void)hipStreamSynchronize(s);
+    for (auto &d : b->desc) {  // the device copy is re-uploaded whole: carry the sweep index
+        d.t = (uint32_t)b->t;
+        d.t_end = 0xFFFFFFFFu;
+    }
     (void)hipFree(b->d_block_img);
     b->d_block_img = nullptr;
     hipError_t e = hipMalloc(&b->d_block_img, block_img.size() * sizeof(int));
@@ -158,8 +161,12 @@ int reset_run(pca_batch *b, const float *const *obs, hipStream_t s)
         if (e != hipSuccess) return hip_fail(e, "batch: initialisation");
         b->count[i] = 0;
         b->tallies[i] = 0;
+        d.t = 0;
+        d.t_end = 0xFFFFFFFFu;
     }
-    hipError_t e = hipMemsetAsync(b->d_t, 0, sizeof(uint32_t), s);
+    hipError_t e = hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size() * sizeof(pcak::ImageDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "batch: initialisation");
     b->t = 0;
     return PCA_OK;
@@ -178,7 +185,6 @@ void release(pca_batch *b)
     (void)hipFree(b->d_desc);
     (void)hipFree(b->d_beta);
     (void)hipFree(b->d_block_img);
-    (void)hipFree(b->d_t);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
 }
@@ -207,11 +213,11 @@ int check_guards(const pca_batch *b, int32_t n, std::vector<int64_t> *add_count,
 int enqueue_eager(pca_batch *b, int32_t n, hipStream_t s)
 {
     for (int32_t i = 0; i < n; ++i) {
-        pcak::BatchLaunch bl{b->d_desc, b->d_block_img, b->d_t, (uint32_t)i};
+        pcak::BatchLaunch bl{b->d_desc, b->d_block_img, (uint32_t)i};
         hipError_t e = pcak::launch_batch_sweep(bl, b->total_blocks, b->cfg.G, b->cfg.share, b->cfg.tiled, b->nbr, s);
         if (e != hipSuccess) return hip_fail(e, "batch sweep");
     }
-    hipError_t e = pcak::launch_advance(b->d_t, (uint32_t)n, s);
+    hipError_t e = pcak::launch_advance(b->d_desc, b->n, (uint32_t)n, s);
     return e == hipSuccess ? PCA_OK : hip_fail(e, "batch sweep");
 }
 
@@ -278,7 +284,6 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
     }
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&b->d_desc, n * sizeof(pcak::ImageDesc));
-    if (e == hipSuccess) e = hipMalloc(&b->d_t, sizeof(uint32_t));
     if (e == hipSuccess && !betas.empty()) e = hipMalloc(&b->d_beta, betas.size() * sizeof(double));
     for (int i = 0; i < n && e == hipSuccess; ++i) {
         const pca_params &p = params[i];

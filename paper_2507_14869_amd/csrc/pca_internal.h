@@ -58,20 +58,21 @@ struct ImageDesc {
     int tpp;              // threads per pixel (Cp / G) in the launch configuration in use
     int block_base;       // first workgroup of this lattice in the batched grid
     int tiles_w;          // tiled traversal: tiles per tile row
+    uint32_t t;           // sweep index before the current replay; advanced on the device
+    uint32_t t_end;       // the lattice stops advancing at this sweep index
 };
 
 struct BatchLaunch {
     const ImageDesc *imgs;
-    const int *block_img;   // workgroup -> lattice
-    const uint32_t *t_dev;  // sweep index of the batch before this graph replay
-    uint32_t toff;          // sweep offset of this launch within the replay
+    const int *block_img;  // workgroup -> lattice
+    uint32_t toff;         // sweep offset of this launch within the replay
 };
 
 constexpr int kTileW = 16;  // tiled traversal: tiles 16 pixels wide, kBlock / tpp pixels each
 
 hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr,
                               hipStream_t s);
-hipError_t launch_advance(uint32_t *t_dev, uint32_t n, hipStream_t s);
+hipError_t launch_advance(ImageDesc *imgs, int n_imgs, uint32_t n, hipStream_t s);
 
 // Shared by the single-lattice and batch entry points (pca_api.hip).
 int validate_params(const pca_params *p);     // PCA_OK or PCA_EINVAL with the error message set

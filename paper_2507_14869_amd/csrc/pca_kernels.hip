@@ -26,6 +26,8 @@
 //               Philox4x32-10 word for counter {pixel, t, chain/4, 0}.
 #include "pca_internal.h"
 
+#include <cstdlib>
+
 namespace pcak {
 namespace {
 
@@ -210,9 +212,9 @@ __device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nb
 
 // One thread's site updates: pixel (r, c) = pix, chains grp*G .. grp*G+G-1.  `q` is the
 // thread's position in its group of SHARE lanes serving the same pixel.
-template <int G, int NBR, int SUB, int NBLK, int SHARE>
+template <int G, int NBR, int SUB, int NBLK, int SHARE, bool DL = false>
 __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab, SweepConsts kc, int pix, int r,
-                                           int c, int grp, int q)
+                                           int c, int grp, int q, const float *drow = nullptr)
 {
     constexpr int NW = NBR / 4;
     const float R = kc.R;
@@ -271,7 +273,7 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         nb[ch].cb = 2 * csum;
         // Stay weight of the lazy conditional.
         const float ex = gp - (float)xs[ch];
-        const float Dx = exp2s(__builtin_fmaf(-a2, ex * ex, m));
+        const float Dx = DL ? drow[xs[ch]] : exp2s(__builtin_fmaf(-a2, ex * ex, m));
         const float Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)xs[ch] * 0x01010101u);
         stay[ch] = (Dx * Px) * R;
         acc[ch] = stay[ch];
@@ -312,7 +314,13 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         for (int b = 0; b < NBLK; ++b) {
             if (b < nblk) {
                 const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
-                if (kend == SUB) {
+                if constexpr (DL) {
+#pragma unroll 4
+                    for (int i = 0; i < kend; ++i) {
+                        level_update<G, NW>(pt, nb, acc, drow[b * SUB + i], kk);
+                        kk += 0x01010101u;
+                    }
+                } else if (kend == SUB) {
 #pragma unroll 2
                     for (int i = 0; i < SUB; i += SHARE) {
                         const float e = gp - kq;
@@ -368,8 +376,13 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
                     k = k0 + kend - 1;
                     uint32_t kk2 = (uint32_t)k0 * 0x01010101u;
                     for (int i = 0; i < kend; ++i) {
-                        const float e = gp - (float)(k0 + i);
-                        const float D = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        float D;
+                        if constexpr (DL) {
+                            D = drow[k0 + i];
+                        } else {
+                            const float e = gp - (float)(k0 + i);
+                            D = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        }
                         const float P = prior_lookup<NW>(pt, nb[ch], kk2);
                         s = __builtin_fmaf(D, P, s);
                         if (s > tf) {
@@ -472,12 +485,27 @@ __global__ __launch_bounds__(kBlock) void mean_kernel(const uint32_t *sum, float
     out[pix] = (float)(vmin + ((double)sum[pix] / (double)count) * delta);
 }
 
+// Marginal mode of kMpmRows pixels per workgroup: their histogram rows (contiguous in
+// memory) are staged through LDS with coalesced loads, then one thread per pixel scans
+// its row; ties go to the lowest level.
+constexpr int kMpmRows = 64;
+
 __global__ __launch_bounds__(kBlock) void mpm_kernel(const uint32_t *hist, uint8_t *out, int64_t N, int L,
                                                      int hist_words)
 {
-    const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (pix >= N) return;
-    const uint32_t *h = hist + pix * hist_words;
+    __shared__ uint32_t rows[kMpmRows * 129];  // row stride hist_words + 1 (<= 129) against bank conflicts
+    const int64_t pix0 = (int64_t)blockIdx.x * kMpmRows;
+    const int nrows = (int)((N - pix0) < kMpmRows ? (N - pix0) : kMpmRows);
+    const int stride = hist_words + 1;
+    const uint32_t *src = hist + pix0 * hist_words;
+    const int words = nrows * hist_words;
+    for (int w = threadIdx.x; w < words; w += kBlock) {
+        const int rr = w / hist_words;
+        rows[rr * stride + (w - rr * hist_words)] = src[w];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x >= nrows) return;
+    const uint32_t *h = rows + threadIdx.x * stride;
     int best = 0;
     uint32_t bestv = h[0] & 0xFFFFu;
     for (int k = 1; k < L; ++k) {
@@ -487,22 +515,61 @@ __global__ __launch_bounds__(kBlock) void mpm_kernel(const uint32_t *hist, uint8
             best = k;
         }
     }
-    out[pix] = (uint8_t)best;
+    out[pix0 + threadIdx.x] = (uint8_t)best;
+}
+
+// One sweep of one lattice with the pixels' data factors in an LDS table: the Cp/G lanes
+// of a pixel evaluate its L data factors once (interleaved by level), every chain's level
+// loop and block re-run then read them.  128-thread workgroups; the table takes
+// (128 / tpp) * (L + 1) floats of dynamic LDS (rows padded against bank conflicts).
+template <int G, int NBR>
+__global__ __launch_bounds__(128) void sweep_kernel_dl(SweepArgs a)
+{
+    extern __shared__ float lds[];  // prior table (NBR*T+1, padded to 4) then the data table
+    float *ptab = lds;
+    float *dtab = lds + ((NBR * a.T + 1 + 3) & ~3);
+    const SweepConsts kc = sweep_prologue(a, NBR, ptab);
+    const int tpp = a.Cp / G;
+    const int L = a.L;
+    const int64_t N = (int64_t)a.H * a.W;
+    const int64_t gid = (int64_t)blockIdx.x * 128 + threadIdx.x;
+    const bool valid = gid < N * tpp;
+    const int pix = valid ? (int)(gid / tpp) : 0;
+    const int grp = valid ? (int)(gid - (int64_t)pix * tpp) : 0;
+    float *drow = dtab + (threadIdx.x / tpp) * (L + 1);
+    if (valid) {
+        const float gp = a.gp[pix];
+        float khat = __builtin_rintf(gp);
+        khat = khat < 0.0f ? 0.0f : khat;
+        khat = khat > (float)(L - 1) ? (float)(L - 1) : khat;
+        const float e0 = gp - khat;
+        const float m = kc.a2 * (e0 * e0);
+        for (int k = grp; k < L; k += tpp) {
+            const float e = gp - (float)k;
+            drow[k] = exp2s(__builtin_fmaf(-kc.a2, e * e, m));
+        }
+    }
+    __syncthreads();
+    if (!valid) return;
+    const int r = pix / a.W;
+    sweep_site<G, NBR, 16, 16, 1, true>(a, ptab, kc, pix, r, pix - r * a.W, grp, 0, drow);
 }
 
 // ---------------------------------------------------------------- batched sweep
 
 // One sweep of every lattice of a batch in one launch.  Each workgroup belongs to one
 // lattice (its descriptor is read once, uniformly); lattices may differ in size, level
-// count, chains, parameters and seed.  The sweep index comes from device memory so a
-// captured graph of n launches can be replayed for the next n sweeps.
+// count, chains, parameters, seed and sweep index.  The sweep index lives in the
+// descriptor in device memory, so a captured graph of n launches can be replayed for the
+// next n sweeps; a lattice whose index reached its end is skipped.
 template <int G, int SHARE, int TILED, int NBR>
 __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
     const int img = b.block_img[blockIdx.x];
     const ImageDesc &d = b.imgs[img];
-    const uint32_t t = *b.t_dev + b.toff;
+    const uint32_t t = d.t + b.toff;
+    if (t >= d.t_end) return;  // this lattice has finished (uniform over the workgroup)
     SweepArgs a;
     a.gp = d.gp;
     a.xin = (t & 1u) ? d.x1 : d.x0;
@@ -553,9 +620,13 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
     else sweep_site<G, NBR, 16, 16, SHARE>(a, ptab, kc, pix, r, c, grp, q);
 }
 
-__global__ void advance_kernel(uint32_t *t_dev, uint32_t n)
+__global__ void advance_kernel(ImageDesc *imgs, int n_imgs, uint32_t n)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *t_dev += n;
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i >= n_imgs) return;
+    const uint32_t t = imgs[i].t;
+    const uint32_t room = imgs[i].t_end > t ? imgs[i].t_end - t : 0u;
+    imgs[i].t = t + (n < room ? n : room);
 }
 
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
@@ -593,6 +664,16 @@ template <int G, int NBR>
 hipError_t launch_sweep_g(const SweepArgs &a, hipStream_t s)
 {
     const int tpp = a.Cp / G;
+    static const int use_dl = [] {
+        const char *v = getenv("PCA_SWEEP_DATA_TABLE");
+        return v ? atoi(v) : 0;
+    }();
+    if (use_dl && a.L > 16 && tpp >= 4) {
+        const size_t shm = ((size_t)((NBR * a.T + 1 + 3) & ~3) + (size_t)(128 / tpp) * (a.L + 1)) * sizeof(float);
+        const int64_t threads = (int64_t)a.H * a.W * tpp;
+        hipLaunchKernelGGL((sweep_kernel_dl<G, NBR>), dim3((unsigned)((threads + 127) / 128)), dim3(128), shm, s, a);
+        return hipGetLastError();
+    }
     if constexpr (G == 4) {
         if (tpp % 4 == 0) return launch_sweep_gs<G, NBR, 4>(a, s);
         if (tpp % 2 == 0) return launch_sweep_gs<G, NBR, 2>(a, s);
@@ -631,9 +712,9 @@ hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int
     return launch_batch_gs<1, 1>(b, total_blocks, tiled, nbr, s);
 }
 
-hipError_t launch_advance(uint32_t *t_dev, uint32_t n, hipStream_t s)
+hipError_t launch_advance(ImageDesc *imgs, int n_imgs, uint32_t n, hipStream_t s)
 {
-    hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, t_dev, n);
+    hipLaunchKernelGGL(advance_kernel, dim3((unsigned)((n_imgs + 63) / 64)), dim3(64), 0, s, imgs, n_imgs, n);
     return hipGetLastError();
 }
 
@@ -664,7 +745,8 @@ hipError_t launch_mean(const uint32_t *sum, float *out, int64_t N, int64_t count
 
 hipError_t launch_mpm(const uint32_t *hist, uint8_t *out, int64_t N, int L, int hist_words, hipStream_t s)
 {
-    hipLaunchKernelGGL(mpm_kernel, dim3(grid_for(N)), dim3(kBlock), 0, s, hist, out, N, L, hist_words);
+    const unsigned blocks = (unsigned)((N + kMpmRows - 1) / kMpmRows);
+    hipLaunchKernelGGL(mpm_kernel, dim3(blocks), dim3(kBlock), 0, s, hist, out, N, L, hist_words);
     return hipGetLastError();
 }
 

@@ -84,3 +84,21 @@ def test_q_zero_is_synchronous_product_of_gibbs_conditionals():
         for i in range(m.H * m.W):
             row *= exact.site_conditional(m, X[a], i, inertia=False)[X[:, i]]
         assert np.allclose(P[a], row, atol=1e-15)
+
+
+def test_halved_coupling_and_doubled_variance_target_the_posterior_as_q_grows():
+    """Since the q -> infinity limit squares the Gibbs law, running the PCA with J/2 and
+    sigma*sqrt(2) makes that limit the posterior itself (the correction offered by
+    paper_2507_14869_amd.variants.posterior_matched)."""
+    from paper_2507_14869_amd.variants import posterior_matched
+    base = dict(CASES[0])
+    target = exact.gibbs_posterior(_model(**base))
+    d_plain, d_matched = [], []
+    for q in (2.0, 4.0, 8.0):
+        m = _model(**{**base, "q": q})
+        d_plain.append(exact.tv(exact.pca_closed_form(m), target))
+        adj = posterior_matched({"J": base["J"], "sigma": base["sigma"]})
+        mm = _model(**{**base, "q": q, "J": adj["J"], "sigma": adj["sigma"]})
+        d_matched.append(exact.tv(exact.pca_closed_form(mm), target))
+    assert d_matched[0] > d_matched[1] > d_matched[2]
+    assert d_matched[2] < 2e-3 < d_plain[2]

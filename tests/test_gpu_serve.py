@@ -1,0 +1,123 @@
+"""Continuous-batching server: requests admitted by device-memory footprint while others
+run, their sweeps interleaved in shared launches; every result must equal the request
+run alone (and the CPU oracle for a small one)."""
+import numpy as np
+import pytest
+
+try:  # import at collection so the first GPU test's time limit does not include it
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover
+    torch = None
+
+from tests.gpu_util import gpu_sampler, oracle_run, torch_cuda
+from tests.test_gpu_batch import _problem
+
+pytestmark = pytest.mark.gpu
+
+
+def _server(budget, max_active=64, k=4, step_ms=0.05):
+    torch_cuda()
+    from paper_2507_14869_amd import Server
+    return Server(budget, max_active=max_active, sweeps_per_step=k, step_ms=step_ms)
+
+
+def _alone(obs, kw, sweeps):
+    s = gpu_sampler(obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(sweeps)
+    out = (s.posterior_mean().cpu().numpy(), s.marginal_map().cpu().numpy(), s.state().cpu().numpy())
+    s.close()
+    return out
+
+
+SPECS = [(37, 53, 256, 2, 1, 9), (64, 64, 2, 2, 2, 14), (17, 200, 16, 2, 3, 6), (90, 33, 256, 2, 5, 11),
+         (128, 96, 16, 2, 6, 7), (5, 7, 33, 2, 7, 13), (40, 40, 2, 4, 8, 10), (33, 65, 256, 1, 9, 8)]
+
+
+@pytest.mark.parametrize("step_ms,k", [(0.05, 3), (2.0, 16)])
+def test_requests_in_the_mix_equal_requests_alone(step_ms, k):
+    sv = _server(budget=1 << 34, k=k, step_ms=step_ms)
+    reqs = {}
+    pending = list(SPECS)
+    # submit half, run a step, submit the rest while the first ones are on the GPU
+    for spec in pending[:4]:
+        obs, kw = _problem(*spec[:4], seed=spec[4])
+        reqs[sv.submit(obs, spec[5], **kw)] = (obs, kw, spec[5])
+    sv.step()
+    done = set(sv.completed())
+    assert sv.stats()[1] + len(done) == 4  # admitted at once: running or already finished
+    for spec in pending[4:]:
+        obs, kw = _problem(*spec[:4], seed=spec[4])
+        reqs[sv.submit(obs, spec[5], **kw)] = (obs, kw, spec[5])
+    for _ in range(100):
+        sv.step()
+        done.update(sv.completed())
+        if len(done) == len(reqs):
+            break
+    assert done == set(reqs)
+    q, a, used, steps, _ = sv.stats()
+    assert (q, a, used) == (0, 0, 0)
+    for rid, (obs, kw, sweeps) in reqs.items():
+        mean, mpm, state = sv.result(rid)
+        ref = _alone(obs, kw, sweeps)
+        assert np.array_equal(mean, ref[0]), rid
+        assert np.array_equal(mpm, ref[1]), rid
+        assert np.array_equal(state, ref[2]), rid
+        assert sv.status(rid) == (2, sweeps)
+    sv.close()
+
+
+def test_memory_budget_queues_requests_and_keeps_results(orc):
+    specs = SPECS[:5]
+    probs = [_problem(*s[:4], seed=s[4]) for s in specs]
+    from paper_2507_14869_amd import Server  # noqa: F401
+    # a budget that holds the largest request but never all of them together
+    sizes = []
+    for (obs, kw), s in zip(probs, specs):
+        H, W = obs.shape
+        L = kw["levels"]
+        Cp = kw["chains"] if kw["chains"] <= 2 else (kw["chains"] + 3) // 4 * 4
+        sizes.append(H * W * (4 + 2 * Cp + 4 + 4 + ((L + 1) // 2) * 4) + 4096 + 8 * 3)
+    budget = max(sizes) + min(sizes)
+    sv = _server(budget=budget, max_active=8, k=5)
+    ids = [sv.submit(obs, s[5], **kw) for (obs, kw), s in zip(probs, specs)]
+    queued_while_running = False
+    done = []
+    for _ in range(200):
+        sv.step()
+        q, a, used, _, _ = sv.stats()
+        assert used <= budget
+        queued_while_running |= q > 0 and a > 0
+        done += sv.completed()
+        if len(done) == len(ids):
+            break
+    assert sorted(done) == sorted(ids)
+    assert queued_while_running  # the budget held requests back until others finished
+    for rid, (obs, kw), s in zip(ids, probs, specs):
+        mean, mpm, state = sv.result(rid)
+        ref = _alone(obs, kw, s[5])
+        assert np.array_equal(mean, ref[0]) and np.array_equal(mpm, ref[1]) and np.array_equal(state, ref[2])
+    # and one against the CPU oracle directly
+    obs, kw = probs[2]
+    ref = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(specs[2][5])
+    mean, mpm, state = sv.result(ids[2])
+    assert np.array_equal(mean, ref.posterior_mean()) and np.array_equal(state, ref.state)
+    sv.release(ids[0])
+    with pytest.raises(Exception):
+        sv.status(ids[0])
+    sv.close()
+
+
+def test_server_rejects_bad_requests():
+    from paper_2507_14869_amd import PcaError
+    sv = _server(budget=1 << 20)
+    obs, kw = _problem(64, 64, 256, 2, 3)
+    with pytest.raises(PcaError):  # 64x64 with L=256 histogram needs more than 1 MiB
+        sv.submit(obs, 5, **kw)
+    small, kw2 = _problem(8, 8, 16, 2, 4)
+    with pytest.raises(PcaError):
+        sv.submit(small, 0, **kw2)
+    rid = sv.submit(small, 3, **kw2)
+    with pytest.raises(PcaError):
+        sv.result(rid)  # not finished
+    while sv.status(rid)[0] != 2:
+        sv.step()
+    sv.close()
