@@ -45,6 +45,7 @@ class _Params(ctypes.Structure):
         ("beta", ctypes.POINTER(ctypes.c_float)), ("beta_len", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("init_mode", ctypes.c_int32), ("burn_in", ctypes.c_int32), ("tally_stride", ctypes.c_int32),
+        ("inertia", ctypes.c_int32),
     ]
 
 
@@ -68,6 +69,7 @@ class Params:
     init_mode: int = 0
     burn_in: int = 0
     tally_stride: int = 0
+    inertia: int = 0
 
     def __post_init__(self):
         if self.vmax is None:
@@ -123,7 +125,7 @@ class _Bound:
             p.height, p.width, p.levels, p.chains, p.neighbourhood, p.prior, p.trunc,
             p.J, p.q, p.sigma, p.vmin, p.vmax,
             _ptr(self.beta, ctypes.c_float) if self.beta.size else None, int(self.beta.size),
-            p.seed & 0xFFFFFFFFFFFFFFFF, p.init_mode, p.burn_in, p.tally_stride)
+            p.seed & 0xFFFFFFFFFFFFFFFF, p.init_mode, p.burn_in, p.tally_stride, p.inertia)
 
     @property
     def ref(self):

@@ -57,6 +57,17 @@
  *  C6  Philox4x32-10 (Salmon et al., SC'11): counter {pixel, sweep, chain>>2, stream},
  *      key {seed lo, seed hi}, word chain&3; stream 0 = updates, 1 = random init.
  *  C7  Gibbs uses the same C1-C6 with R = 0, reading the partially updated state.
+ *  C8  Inertia norms (Sec. 3, "The lazy PCA": the inertia q|x_i - w_i|^p, with 0^0 = 0;
+ *      L1 and L2 offered at the end of Sec. 5.2).  p = 0 is C4.  For p = 1 or 2 the data
+ *      and inertia terms share one exponent, shifted by its maximum over the levels so
+ *      that the product cannot underflow where both terms are large:
+ *        F_k = fmaf(-a2, e_k*e_k, -(q2 * (float)d_k^p)),  d_k = |k - x|,
+ *        E_k = exp2s(F_k - Fmax),  acc_{-1} = 0,  acc_k = fmaf(E_k, P(S_k), acc_{k-1}),
+ *      drawn as in C5 (the stay branch never fires).  F is concave in k, so Fmax is the
+ *      larger of F at k1 = clamp(floor(kc), 0, L-1) and k2 = min(k1 + 1, L-1), where kc
+ *      maximises the real-valued form: for p = 1, kc = min(max(x, g' - h), g' + h) with
+ *      h = q2 / (2*a2); for p = 2, kc = (a2*g' + q2*x) / (a2 + q2).  Gibbs has no
+ *      inertia at any p.
  */
 #include <math.h>
 #include <stdint.h>
@@ -78,6 +89,7 @@ typedef struct {
     int32_t beta_len;  /* sweeps past the end reuse the last value */
     uint64_t seed;
     int32_t init_mode, burn_in, tally_stride;
+    int32_t inertia;   /* exponent p of the inertia norm: 0 (indicator), 1 or 2 */
 } orc_params;
 
 /* ------------------------------------------------------------------ Philox (C6) */
@@ -161,7 +173,8 @@ typedef struct {
 } orc_run_consts;
 
 typedef struct {
-    float c2, R;
+    float c2, q2, R;
+    int p; /* inertia exponent; 0 also for Gibbs */
 } orc_sweep_consts;
 
 static int check_params(const orc_params *p)
@@ -183,6 +196,7 @@ static int check_params(const orc_params *p)
     if (p->beta_len == 0 && (double)p->q * ORC_LOG2E > 100.0) return ORC_EINVAL;
     if (p->init_mode != 0 && p->init_mode != 1) return ORC_EINVAL;
     if (p->burn_in < 0 || p->tally_stride < 0) return ORC_EINVAL;
+    if (p->inertia < 0 || p->inertia > 2) return ORC_EINVAL;
     return ORC_OK;
 }
 
@@ -214,8 +228,9 @@ static orc_sweep_consts sweep_consts(const orc_params *p, int64_t t, int gibbs)
     double beta = beta_at(p, t);
     double kappa = p->prior == 0 ? 2.0 : 1.0;
     sc.c2 = (float)(((beta * (double)p->J) * kappa) * ORC_LOG2E);
-    float q2 = (float)((beta * (double)p->q) * ORC_LOG2E);
-    sc.R = gibbs ? 0.0f : orc_exp2s(q2) - 1.0f;
+    sc.q2 = (float)((beta * (double)p->q) * ORC_LOG2E);
+    sc.p = gibbs ? 0 : p->inertia;
+    sc.R = gibbs ? 0.0f : orc_exp2s(sc.q2) - 1.0f;
     return sc;
 }
 
@@ -240,6 +255,15 @@ static float data_factor(float gp, int k, int L, float a2)
 
 static float prior_factor(int S, float c2) { return orc_exp2s(-(c2 * (float)S)); }
 
+/* F_k of C8: data exponent plus inertia exponent q2 |k - x|^p, in log2 units. */
+static float inertia_exponent(float gp, int k, int x, int p, float a2, float q2)
+{
+    int d = abs(k - x);
+    int dp = p == 1 ? d : d * d;
+    float e = gp - (float)k;
+    return fmaf(-a2, e * e, -(q2 * (float)dp));
+}
+
 /* S_k = sum over in-lattice neighbours j of min(|k - x_j|, T); `plane` is one chain's
  * [H][W] state. */
 static int neighbour_stat(const orc_run_consts *rc, const uint8_t *plane, int r, int c, int k)
@@ -263,6 +287,29 @@ static void site_acc(const orc_run_consts *rc, const orc_sweep_consts *sc, const
                      int r, int c, float gp, float *acc)
 {
     int x = plane[(size_t)r * rc->W + c];
+    if (sc->p > 0) { /* C8: data and inertia in one shifted exponent, no stay branch */
+        float kc;
+        if (sc->p == 1) {
+            float h = sc->q2 / (2.0f * rc->a2);
+            kc = fminf(fmaxf((float)x, gp - h), gp + h);
+        } else {
+            kc = (rc->a2 * gp + sc->q2 * (float)x) / (rc->a2 + sc->q2);
+        }
+        int k1 = (int)fminf(fmaxf(floorf(kc), 0.0f), (float)(rc->L - 1));
+        int k2 = k1 + 1 < rc->L ? k1 + 1 : k1;
+        float F1 = inertia_exponent(gp, k1, x, sc->p, rc->a2, sc->q2);
+        float F2 = inertia_exponent(gp, k2, x, sc->p, rc->a2, sc->q2);
+        float Fmax = F1 > F2 ? F1 : F2;
+        float a = 0.0f;
+        acc[0] = a;
+        for (int k = 0; k < rc->L; ++k) {
+            float Ek = orc_exp2s(inertia_exponent(gp, k, x, sc->p, rc->a2, sc->q2) - Fmax);
+            float Pk = prior_factor(neighbour_stat(rc, plane, r, c, k), sc->c2);
+            a = fmaf(Ek, Pk, a);
+            acc[1 + k] = a;
+        }
+        return;
+    }
     float Dx = data_factor(gp, x, rc->L, rc->a2);
     float Px = prior_factor(neighbour_stat(rc, plane, r, c, x), sc->c2);
     float a = (Dx * Px) * sc->R;

@@ -5,7 +5,7 @@ natural-log units and float64, and are what the oracle's empirical behaviour is 
 
 * PCA transition (product of single-site conditionals): Sec. 3 eq. (general_pca_definition)
   with the lazy posterior conditional of Sec. 5.2 (inertia compares with the site's own
-  previous value).
+  previous value; indicator by default, or q|k - x_i|^p for p = 1, 2 as in Sec. 3).
 * Closed-form stationary law of a PCA with a symmetric pair Hamiltonian, Sec. 3
   eq. (symm_ham_pca_stationary_measure): pi(x) ~ sum_w exp(-H(x,w)); with the data term
   added symmetrically this is exp(-D(x)) * prod_i Z_i(x).
@@ -34,6 +34,7 @@ class Model:
     sigma: float      # level units
     beta: float
     g: np.ndarray     # [H, W] observation in level units
+    p: int = 0        # inertia exponent: q |k - x_i|^p with 0^0 = 0 (p = 0: indicator)
 
     @property
     def c(self) -> float:
@@ -83,7 +84,8 @@ def log_site_weights(m: Model, x: np.ndarray, i: int, inertia: bool) -> np.ndarr
         S += np.minimum(np.abs(k - x[j]), m.Teff)
     lw = -m.c * S - m.a * (g - k) ** 2
     if inertia:
-        lw = lw - m.beta * m.q * (k != x[i])
+        d = np.abs(k - x[i]).astype(np.float64)
+        lw = lw - m.beta * m.q * ((d != 0) if m.p == 0 else d ** m.p)
     return lw
 
 

@@ -10,10 +10,10 @@ import pytest
 from tests import exact
 
 
-def _model(H, W, L, nbr, potts, T, J, q, sigma, beta, seed):
+def _model(H, W, L, nbr, potts, T, J, q, sigma, beta, seed, p=0):
     rng = np.random.default_rng(seed)
     g = rng.uniform(-0.3, L - 0.7, size=(H, W)).astype(np.float32).astype(np.float64)
-    return exact.Model(H=H, W=W, L=L, nbr=nbr, potts=potts, T=T, J=J, q=q, sigma=sigma, beta=beta, g=g)
+    return exact.Model(H=H, W=W, L=L, nbr=nbr, potts=potts, T=T, J=J, q=q, sigma=sigma, beta=beta, g=g, p=p)
 
 
 CASES = [
@@ -23,6 +23,9 @@ CASES = [
     dict(H=2, W=3, L=3, nbr=8, potts=False, T=1, J=0.5, q=0.7, sigma=0.9, beta=1.3, seed=2),
     # 2x2 with 4 levels, truncated linear T=2, 4 neighbours (256 states)
     dict(H=2, W=2, L=4, nbr=4, potts=False, T=2, J=0.8, q=0.4, sigma=1.1, beta=0.8, seed=3),
+    # the L1 and L2 inertia norms of Sec. 3 on the 2x3 and 2x2 lattices
+    dict(H=2, W=3, L=3, nbr=8, potts=False, T=1, J=0.5, q=0.7, sigma=0.9, beta=1.3, seed=2, p=1),
+    dict(H=2, W=2, L=4, nbr=4, potts=False, T=2, J=0.8, q=0.4, sigma=1.1, beta=0.8, seed=3, p=2),
 ]
 
 
@@ -102,3 +105,26 @@ def test_halved_coupling_and_doubled_variance_target_the_posterior_as_q_grows():
         d_matched.append(exact.tv(exact.pca_closed_form(mm), target))
     assert d_matched[0] > d_matched[1] > d_matched[2]
     assert d_matched[2] < 2e-3 < d_plain[2]
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_large_q_limit_is_squared_gibbs_law_for_every_norm(p):
+    """Any inertia that vanishes only at k = x_i has the same q -> infinity limit."""
+    base = dict(CASES[2], p=p)
+    d = []
+    for q in (2.0, 4.0, 8.0):
+        m = _model(**{**base, "q": q})
+        d.append(exact.tv(exact.pca_closed_form(m), exact.gibbs_posterior(m, power=2.0)))
+    assert d[0] > d[1] > d[2]
+    assert d[2] < 2e-3
+
+
+def test_norms_coincide_on_binary_lattices_and_differ_beyond():
+    """With two levels |k - x| is 0 or 1, so the indicator, L1 and L2 inertias agree; with
+    four levels a change by 2 costs q, 2q and 4q respectively."""
+    for p in (1, 2):
+        a = _model(**CASES[0])
+        b = _model(**{**CASES[0], "p": p})
+        assert np.array_equal(exact.pca_matrix(a), exact.pca_matrix(b))
+    laws = [exact.pca_closed_form(_model(**{**CASES[2], "p": p})) for p in (0, 1, 2)]
+    assert exact.tv(laws[0], laws[1]) > 1e-3 and exact.tv(laws[1], laws[2]) > 1e-3

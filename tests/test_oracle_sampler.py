@@ -50,6 +50,9 @@ CASES = [
     dict(H=2, W=3, L=3, nbr=8, potts=False, T=1, J=0.5, q=0.7, sigma=0.9, beta=1.3, seed=2, t=5),
     dict(H=2, W=2, L=4, nbr=4, potts=False, T=2, J=0.8, q=0.4, sigma=1.1, beta=0.8, seed=3, t=4),
     dict(H=3, W=2, L=2, nbr=8, potts=True, T=1, J=0.3, q=2.5, sigma=0.6, beta=1.0, seed=4, t=7),
+    # L1 and L2 inertia norms (Sec. 3)
+    dict(H=2, W=3, L=3, nbr=8, potts=False, T=1, J=0.5, q=0.7, sigma=0.9, beta=1.3, seed=2, t=5, p=1),
+    dict(H=2, W=2, L=4, nbr=4, potts=False, T=2, J=0.8, q=0.4, sigma=1.1, beta=0.8, seed=3, t=4, p=2),
 ]
 
 
@@ -58,11 +61,12 @@ def make(case, orc, chains):
     H, W, L = case["H"], case["W"], case["L"]
     g = rng.uniform(-0.3, L - 0.7, size=(H, W)).astype(np.float32)
     m = exact.Model(H=H, W=W, L=L, nbr=case["nbr"], potts=case["potts"], T=case["T"], J=case["J"],
-                    q=case["q"], sigma=case["sigma"], beta=case["beta"], g=g.astype(np.float64))
+                    q=case["q"], sigma=case["sigma"], beta=case["beta"], g=g.astype(np.float64),
+                    p=case.get("p", 0))
     p = orc.Params(height=H, width=W, levels=L, chains=chains, neighbourhood=case["nbr"],
                    prior=orc.POTTS if case["potts"] else orc.TRUNC_LINEAR, trunc=case["T"], J=case["J"],
                    q=case["q"], sigma=case["sigma"], vmin=0.0, vmax=float(L - 1), beta=[case["beta"]],
-                   seed=1000 + case["seed"])
+                   seed=1000 + case["seed"], inertia=case.get("p", 0))
     return m, p, g
 
 
@@ -106,7 +110,7 @@ def test_pca_long_run_matches_closed_form_stationary_law(orc):
 # ------------------------------------------------------------- closed-form special cases
 
 def one_site_probs(orc, L, g_c, nb_vals, *, J=0.0, q=0.0, sigma=1.0, beta=1.0, potts=False, T=1,
-                   x_self=None, nbr=4, pos="centre"):
+                   x_self=None, nbr=4, pos="centre", inertia=0):
     """Conditional of one site of a 3x3 lattice with the given neighbour values."""
     H = W = 3
     st = np.zeros((1, H, W), dtype=np.uint8)
@@ -123,7 +127,7 @@ def one_site_probs(orc, L, g_c, nb_vals, *, J=0.0, q=0.0, sigma=1.0, beta=1.0, p
         st[0, r, c] = x_self
     p = orc.Params(height=H, width=W, levels=L, chains=1, neighbourhood=nbr,
                    prior=orc.POTTS if potts else orc.TRUNC_LINEAR, trunc=T, J=J, q=q, sigma=sigma,
-                   vmin=0.0, vmax=float(L - 1), beta=[beta], seed=9)
+                   vmin=0.0, vmax=float(L - 1), beta=[beta], seed=9, inertia=inertia)
     return orc.site_probs(p, obs, st, 0, r, c)
 
 
@@ -200,6 +204,46 @@ def test_inertia_odds_at_symmetric_observation(orc, beta, q):
     for x in (0, 1):
         p = one_site_probs(orc, 2, 0.5, [0, 0, 0, 0], q=q, beta=beta, sigma=0.8, x_self=x)
         assert abs(p[x] - 1.0 / (1.0 + math.exp(-beta * q))) < 1e-6
+
+
+@pytest.mark.parametrize("p,beta,q", [(1, 1.0, 0.5), (1, 1.5, 1.1), (2, 1.0, 0.3), (2, 2.0, 0.45)])
+def test_inertia_norm_profile_with_flat_data(orc, p, beta, q):
+    """J = 0 and a data term that is flat over the levels (huge sigma): the conditional is
+    exp(-beta q |k - x|^p) normalised, a two-sided geometric law for p = 1 and a discrete
+    Gaussian centred on the current value for p = 2 (Sec. 3 inertia q|x_i - w_i|^p)."""
+    L, x = 13, 5
+    got = one_site_probs(orc, L, 6.0, [0, 0, 0, 0], q=q, beta=beta, sigma=1e4, x_self=x, inertia=p)
+    d = np.abs(np.arange(L) - x).astype(np.float64)
+    want = np.exp(-beta * q * d ** p)
+    assert np.allclose(got, want / want.sum(), rtol=1e-5, atol=3e-7)
+    assert abs(got[x + 1] / got[x] - math.exp(-beta * q)) < 1e-5
+    assert abs(got[x + 2] / got[x] - math.exp(-beta * q * 2 ** p)) < 1e-5
+
+
+def test_inertia_norm_single_site_matches_exact_conditional(orc):
+    rng = np.random.default_rng(15)
+    for _ in range(30):
+        p_ = int(rng.integers(1, 3))
+        L = int(rng.integers(2, 40))
+        nb = rng.integers(0, L, size=4).tolist()
+        x = int(rng.integers(0, L))
+        g_c = float(rng.uniform(-1, L))
+        J, q, sigma, beta, T = rng.uniform(0, 1), rng.uniform(0, 2), rng.uniform(0.3, 4), rng.uniform(0.5, 2), int(
+            rng.integers(1, L + 1))
+        p = one_site_probs(orc, L, g_c, nb, J=J, q=q, sigma=sigma, beta=beta, T=T, x_self=x, inertia=p_)
+        st = np.zeros(9, dtype=np.int64)
+        st[[1, 7, 3, 5]] = nb
+        st[4] = x
+        m = exact.Model(H=3, W=3, L=L, nbr=4, potts=False, T=T, J=J, q=q, sigma=sigma, beta=beta,
+                        g=np.array([[0, 0, 0], [0, np.float32(g_c), 0], [0, 0, 0]], dtype=np.float64), p=p_)
+        want = exact.site_conditional(m, st, 4, inertia=True)
+        # The data and inertia exponents are evaluated in FP32 in log2 units; where they
+        # oppose each other they reach hundreds, and their rounding (2^-24 relative to the
+        # magnitude) becomes a relative error of the weights.
+        k = np.arange(L)
+        F = (m.a * (np.float32(g_c) - k) ** 2 + beta * q * np.abs(k - x) ** p_) / math.log(2)
+        rtol = 1e-6 + 2 * math.log(2) * 2.0 ** -24 * (F[want > 1e-9].max() + F.min())
+        assert np.allclose(p, want, rtol=rtol, atol=3e-7), (p_, L, nb, x)
 
 
 def test_beta_does_not_scale_the_data_term(orc):
@@ -323,7 +367,8 @@ def test_statistics_respect_burn_in_and_tally_stride(orc):
 @pytest.mark.parametrize("bad", [dict(levels=1), dict(levels=257), dict(chains=0), dict(neighbourhood=6),
                                  dict(prior=2), dict(trunc=0), dict(J=-0.1), dict(q=-1.0), dict(sigma=0.0),
                                  dict(vmax=0.0), dict(init_mode=2), dict(burn_in=-1), dict(tally_stride=-1),
-                                 dict(beta=[0.0]), dict(height=0), dict(q=80.0)])
+                                 dict(beta=[0.0]), dict(height=0), dict(q=80.0), dict(inertia=3),
+                                 dict(inertia=-1)])
 def test_invalid_parameters_rejected(orc, bad):
     kw = dict(height=2, width=2, levels=4, chains=1, prior=orc.TRUNC_LINEAR, trunc=1, J=0.1, q=0.5, sigma=1.0,
               vmin=0.0, vmax=3.0)
