@@ -28,14 +28,18 @@ sys.path.insert(0, ROOT)
 # i.e. 256 CUs x 128 lanes x 2.4 GHz = 78.6 T lane-operations/s.
 PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2507_14869_amd", "csrc", "pca_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_14869_amd", "csrc", f) for f in ("pca_sweep.h", "pca_kernels.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c3_traffic.txt")
 
 
-def valu_ops_per_site_update(levels: int, chains: int) -> float:
-    """Algorithmic VALU lane-ops per site update: per (chain, level) three byte-SADs, the
-    two-op table index and one fma; per (pixel, level) the 15-op data factor shared by
-    the chains of the pixel."""
+def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0) -> float:
+    """Algorithmic VALU lane-ops per site update.  Indicator inertia: per (chain, level)
+    three byte-SADs, the two-op table index and one fma; per (pixel, level) the 15-op data
+    factor shared by the chains of the pixel.  L1/L2 inertia: per (chain, level) those six
+    plus |k - x|^p and its conversion (3), the exponent (2 fma/mul, 1 subtraction) and
+    exp2s (9); per (pixel, level) e and e*e (2)."""
+    if inertia:
+        return levels * (21.0 + 2.0 / chains)
     return levels * (6.0 + 15.0 / chains)
 
 
@@ -49,8 +53,12 @@ def hbm_bytes_per_sweep(N: int, chains: int, tally: bool) -> float:
 
 
 def kernel_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the sources the single-lattice sweep kernel is built from."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(per_launch_units: float):
@@ -71,11 +79,11 @@ def measured_traffic(per_launch_units: float):
         return None
 
 
-def cpu_baseline(wl, seconds: float):
+def cpu_baseline(wl, seconds: float, inertia: int = 0):
     """The oracle on sampled site updates of sweep 0 of the same workload, single thread."""
     import numpy as np
     import oracle
-    p = oracle.Params(**wl.params())
+    p = oracle.Params(**wl.params(inertia=inertia))
     x0 = oracle.init_state(p, wl.obs)
     rng = np.random.default_rng(7)
     N = wl.height * wl.width
@@ -89,8 +97,8 @@ def cpu_baseline(wl, seconds: float):
         done += n
     dt = time.perf_counter() - t0
     return {"value": done / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"{done} random (chain, pixel) site updates of sweep 0 of the same 2048x2048 L=256 "
-                      f"workload, {dt:.1f} s single-threaded"}
+            "sample": f"{done} random (chain, pixel) site updates of sweep 0 of the same {wl.height}x{wl.width} "
+                      f"L={wl.levels} workload, {dt:.1f} s single-threaded"}
 
 
 def copy_probe(mib: int, reps: int = 4):
@@ -313,6 +321,9 @@ def main():
     ap.add_argument("--requests", type=int, default=250, help="c5: number of requests in the trace")
     ap.add_argument("--step-ms", type=float, default=20.0, help="c5: GPU time per server step")
     ap.add_argument("--sweeps", type=int, default=None, help="override the workload's sweep count")
+    ap.add_argument("--inertia", type=int, default=0, choices=[0, 1, 2],
+                    help="c1-c3: inertia norm exponent (0 indicator, 1 L1, 2 L2)")
+    ap.add_argument("--q", type=float, default=None, help="c1-c3: override the inertia weight q")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -340,10 +351,12 @@ def main():
         return
 
     wl = synth.make_workload(args.workload, sweeps=args.sweeps)
+    if args.q is not None:
+        wl.q = args.q
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     obs = torch.from_numpy(wl.obs).to(dev)
-    kw = wl.params()
+    kw = wl.params(inertia=args.inertia)
     kw.pop("height")
     kw.pop("width")
     levels = kw.pop("levels")
@@ -386,10 +399,10 @@ def main():
     su_total = wl.site_updates * args.steps
     value = su_total / elapsed
 
-    ops_per_su = valu_ops_per_site_update(wl.levels, wl.chains)
+    ops_per_su = valu_ops_per_site_update(wl.levels, wl.chains, args.inertia)
     launch_ops = ops_per_su * N * wl.chains
     achieved = launch_ops / avg_launch_s / 1e12
-    traffic = measured_traffic(N * wl.chains)
+    traffic = measured_traffic(N * wl.chains) if args.inertia == 0 and wl.name == "c3" else None
     hbm_alg = hbm_bytes_per_sweep(N, wl.chains, wl.tally_stride > 0)
     out = {
         "metric": "site-updates/s",
@@ -407,7 +420,9 @@ def main():
         "config": {
             "workload": f"{wl.name}: {wl.height}x{wl.width} image, L={wl.levels}, {wl.chains} chains, "
                         f"{wl.sweeps} sweeps, truncated-linear prior T={wl.trunc} J={wl.J} q={wl.q}, "
-                        f"sigma={wl.sigma} levels, 4-neighbour, mean + marginal mode",
+                        f"sigma={wl.sigma} levels, 4-neighbour, mean + marginal mode"
+                        + ("" if args.inertia == 0 else f", L{args.inertia} inertia"),
+            "inertia": args.inertia,
             "height": wl.height, "width": wl.width, "levels": wl.levels, "chains": wl.chains,
             "sweeps": wl.sweeps, "site_updates_per_step": wl.site_updates,
         },
@@ -431,7 +446,7 @@ def main():
         "level_evaluations_per_s": value * wl.levels,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.inertia)
     print(json.dumps(out), flush=True)
 
 

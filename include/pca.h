@@ -61,7 +61,7 @@ typedef struct {
     int32_t prior;         /* PCA_PRIOR_* */
     int32_t trunc;         /* truncation T >= 1 of the linear prior (ignored for Potts) */
     float J;               /* pair coupling >= 0 */
-    float q;               /* inertia >= 0: log-odds penalty beta*q for a changed site (L0 norm, Sec. 5.2) */
+    float q;               /* inertia weight >= 0: a change of a site from x to k costs beta*q*|k-x|^p (Sec. 3) */
     float sigma;           /* noise standard deviation > 0, value units */
     float vmin, vmax;      /* values of levels 0 and L-1, vmax > vmin */
     const float *beta;     /* host array of per-sweep inverse temperatures (> 0), copied at init; NULL => 1 */
@@ -70,6 +70,8 @@ typedef struct {
     int32_t init_mode;     /* 0: every chain starts at the level nearest the observation; 1: uniform random */
     int32_t burn_in;       /* sweeps with index < burn_in are not accumulated */
     int32_t tally_stride;  /* histogram every tally_stride-th sweep from burn_in on; 0 = no histogram */
+    int32_t inertia;       /* exponent p of the inertia norm (Sec. 3, with 0^0 = 0): 0 = indicator, the
+                              paper's experiments (Sec. 5.2); 1 = L1; 2 = L2 (both named in Sec. 5.2). */
 } pca_params;
 
 /* Creates a context: validates `params`, allocates the chain states, the mean
@@ -135,8 +137,8 @@ typedef struct pca_batch pca_batch; /* opaque, library-owned */
 
 /* Creates a batch of n >= 1 lattices from params[0..n-1] and the device observations
  * obs_dev[0..n-1] (float32 [height][width] each, read during initialisation only).
- * Errors: PCA_EINVAL (any invalid parameter set, NULL pointer, mixed neighbourhoods),
- * PCA_ENOMEM, PCA_EDEVICE. */
+ * Errors: PCA_EINVAL (any invalid parameter set, NULL pointer, mixed neighbourhoods,
+ * inertia 0 mixed with inertia 1 or 2), PCA_ENOMEM, PCA_EDEVICE. */
 int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_t n, void *stream,
                    pca_batch **out);
 

@@ -37,7 +37,7 @@ class Sampler:
                  prior: int = PCA_PRIOR_TRUNC_LINEAR, trunc: int = 1, J: float = 0.0, q: float = 0.0,
                  sigma: float = 1.0, vmin: float = 0.0, vmax: Optional[float] = None,
                  beta: Sequence[float] = (), seed: int = 0, init_mode: int = 0, burn_in: int = 0,
-                 tally_stride: int = 0, stream=None):
+                 tally_stride: int = 0, inertia: int = 0, stream=None):
         import torch
         _lib.load()
         if obs.dtype != torch.float32 or obs.dim() != 2 or not obs.is_cuda:
@@ -49,7 +49,7 @@ class Sampler:
         self.params, self._beta_buf = make_params(
             height=self.height, width=self.width, levels=levels, chains=chains, neighbourhood=neighbourhood,
             prior=prior, trunc=trunc, J=J, q=q, sigma=sigma, vmin=vmin, vmax=vmax, beta=beta, seed=seed,
-            init_mode=init_mode, burn_in=burn_in, tally_stride=tally_stride)
+            init_mode=init_mode, burn_in=burn_in, tally_stride=tally_stride, inertia=inertia)
         self.ctx = pca_init(self.params, self.obs.data_ptr(), _stream_handle(stream))
 
     def sweep(self, n: int = 1, stream=None) -> "Sampler":

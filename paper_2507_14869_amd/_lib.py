@@ -40,6 +40,7 @@ class pca_params(ctypes.Structure):
         ("beta", ctypes.POINTER(ctypes.c_float)), ("beta_len", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("init_mode", ctypes.c_int32), ("burn_in", ctypes.c_int32), ("tally_stride", ctypes.c_int32),
+        ("inertia", ctypes.c_int32),
     ]
 
 
@@ -110,7 +111,7 @@ def make_params(*, height: int, width: int, levels: int, chains: int = 1, neighb
                 prior: int = PCA_PRIOR_TRUNC_LINEAR, trunc: int = 1, J: float = 0.0, q: float = 0.0,
                 sigma: float = 1.0, vmin: float = 0.0, vmax: Optional[float] = None,
                 beta: Sequence[float] = (), seed: int = 0, init_mode: int = 0, burn_in: int = 0,
-                tally_stride: int = 0):
+                tally_stride: int = 0, inertia: int = 0):
     """A pca_params struct plus the beta buffer it points to (keep both alive)."""
     if vmax is None:
         vmax = float(levels - 1)
@@ -118,7 +119,7 @@ def make_params(*, height: int, width: int, levels: int, chains: int = 1, neighb
     buf = (ctypes.c_float * max(1, len(beta)))(*beta) if beta else None
     p = pca_params(height, width, levels, chains, neighbourhood, prior, trunc, J, q, sigma, vmin, vmax,
                    ctypes.cast(buf, ctypes.POINTER(ctypes.c_float)) if buf is not None else None, len(beta),
-                   seed & 0xFFFFFFFFFFFFFFFF, init_mode, burn_in, tally_stride)
+                   seed & 0xFFFFFFFFFFFFFFFF, init_mode, burn_in, tally_stride, inertia)
     return p, buf
 
 

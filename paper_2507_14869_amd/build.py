@@ -4,13 +4,16 @@ from __future__ import annotations
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpca.so")
-SOURCES = ["pca_kernels.hip", "pca_api.hip", "pca_batch.hip", "pca_serve.hip"]
+SOURCES = ["pca_kernels.hip", "pca_kernels_batch.hip", "pca_kernels_inertia.hip", "pca_api.hip", "pca_batch.hip",
+           "pca_serve.hip"]
+BUILD_DIR = os.path.join(HERE, "_build")
 
 
 def hipcc() -> str:
@@ -29,8 +32,23 @@ def compile_flags():
 
 
 def build(verbose: bool = False) -> str:
+    """Compiles every source to an object file (in parallel), then links the library."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    flags = compile_flags()
+
+    def compile_one(src: str) -> str:
+        obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc(), *flags, "-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        return obj
+
+    jobs = max(1, min(len(SOURCES), os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=jobs) as pool:
+        objs = list(pool.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *compile_flags(), "-shared", "-o", tmp, *[os.path.join(CSRC, s) for s in SOURCES]]
+    cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -21,7 +21,7 @@ struct pca_ctx {
     int64_t N = 0;
     int hist_words = 0;
     float *gp = nullptr;
-    uint8_t *x[2] = {nullptr, nullptr};
+    uint8_t *x[2] = {nullptr, nullptr};  // double-buffered chain states; x[cur] is current
     int cur = 0;
     uint32_t *sum = nullptr;
     uint32_t *hist = nullptr;
@@ -73,6 +73,7 @@ int validate(const pca_params *p)
     if (p->beta_len == 0 && (double)p->q * log2e > 100.0) return fail(PCA_EINVAL, "q too large");
     if (p->init_mode != 0 && p->init_mode != 1) return fail(PCA_EINVAL, "init_mode must be 0 or 1");
     if (p->burn_in < 0 || p->tally_stride < 0) return fail(PCA_EINVAL, "burn_in and tally_stride must be >= 0");
+    if (p->inertia < 0 || p->inertia > 2) return fail(PCA_EINVAL, "inertia must be 0, 1 or 2");
     return PCA_OK;
 }
 
@@ -214,6 +215,7 @@ int pca_sweep(pca_ctx *ctx, int32_t n, void *stream)
     a.J = (double)p.J;
     a.q = (double)p.q;
     a.kappa = p.prior == PCA_PRIOR_POTTS ? 2.0 : 1.0;
+    a.inertia = p.inertia;
     a.sigma_s = (double)p.sigma * level_scale(p);
     a.key0 = (uint32_t)p.seed;
     a.key1 = (uint32_t)(p.seed >> 32);

@@ -45,6 +45,7 @@ struct pca_batch {
     int device = 0;
     int n = 0;
     int nbr = 4;
+    bool inr = false;  // L1/L2 inertia kernels
     std::vector<pca_params> p;
     std::vector<pcak::ImageDesc> desc;  // host copy; pointers are device buffers
     std::vector<int64_t> count, tallies;
@@ -63,6 +64,7 @@ namespace {
 
 bool config_valid(const pca_batch *b, const LaunchConfig &c)
 {
+    if (b->inr && c.share != 1) return false;  // each chain has its own exponent: nothing to share
     for (const auto &d : b->desc) {
         if (d.Cp % c.G != 0) return false;
         const int tpp = d.Cp / c.G;
@@ -214,7 +216,8 @@ int enqueue_eager(pca_batch *b, int32_t n, hipStream_t s)
 {
     for (int32_t i = 0; i < n; ++i) {
         pcak::BatchLaunch bl{b->d_desc, b->d_block_img, (uint32_t)i};
-        hipError_t e = pcak::launch_batch_sweep(bl, b->total_blocks, b->cfg.G, b->cfg.share, b->cfg.tiled, b->nbr, s);
+        hipError_t e = pcak::launch_batch_sweep(bl, b->total_blocks, b->cfg.G, b->cfg.share, b->cfg.tiled, b->nbr,
+                                                b->inr, s);
         if (e != hipSuccess) return hip_fail(e, "batch sweep");
     }
     hipError_t e = pcak::launch_advance(b->d_desc, b->n, (uint32_t)n, s);
@@ -264,11 +267,14 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
         if (!obs_dev[i]) return fail(PCA_EINVAL, "obs_dev[%d] is NULL", i);
         if (params[i].neighbourhood != params[0].neighbourhood)
             return fail(PCA_EINVAL, "all lattices of a batch must use the same neighbourhood");
+        if ((params[i].inertia != 0) != (params[0].inertia != 0))
+            return fail(PCA_EINVAL, "a batch cannot mix the indicator inertia with the L1/L2 norms");
     }
     hipStream_t s = (hipStream_t)stream;
     pca_batch *b = new pca_batch();
     b->n = n;
     b->nbr = params[0].neighbourhood;
+    b->inr = params[0].inertia != 0;
     b->last = s;
     (void)hipGetDevice(&b->device);
     b->p.assign(params, params + n);
@@ -300,6 +306,7 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
         d.J = (double)p.J;
         d.q = (double)p.q;
         d.kappa = p.prior == PCA_PRIOR_POTTS ? 2.0 : 1.0;
+        d.inertia = p.inertia;
         d.sigma_s = (double)p.sigma * level_scale(p);
         d.key0 = (uint32_t)p.seed;
         d.key1 = (uint32_t)(p.seed >> 32);

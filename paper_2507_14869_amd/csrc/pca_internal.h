@@ -28,6 +28,7 @@ struct SweepArgs {
     double beta, J, q, kappa, sigma_s;  // kappa = 2 (Potts) or 1; sigma_s = sigma in level units
     uint32_t key0, key1;  // Philox key (seed split)
     uint32_t t;           // sweep index
+    int inertia;          // inertia norm exponent: 0 (indicator, stay weight), 1 or 2
 };
 
 struct InitArgs {
@@ -53,6 +54,7 @@ struct ImageDesc {
     const double *beta;   // per-sweep beta (device), beta_len entries; none => 1
     int beta_len;
     int H, W, L, C, Cp, T, hist_words, burn_in, tally_stride;
+    int inertia;          // 0, 1 or 2; every lattice of one launch has inertia 0 or none has
     double J, q, kappa, sigma_s;
     uint32_t key0, key1;
     int tpp;              // threads per pixel (Cp / G) in the launch configuration in use
@@ -70,9 +72,15 @@ struct BatchLaunch {
 
 constexpr int kTileW = 16;  // tiled traversal: tiles 16 pixels wide, kBlock / tpp pixels each
 
-hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr,
+// inr: the lattices use the L1/L2 inertia form (share is then ignored).
+hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr, bool inr,
                               hipStream_t s);
 hipError_t launch_advance(ImageDesc *imgs, int n_imgs, uint32_t n, hipStream_t s);
+// The L1/L2 inertia kernels (pca_kernels_inertia.hip); the two launchers above hand over
+// to these when the sweep (or every lattice of the batch) has inertia 1 or 2.
+hipError_t launch_sweep_inertia(const SweepArgs &a, int G, int nbr, hipStream_t s);
+hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int total_blocks, int G, int tiled, int nbr,
+                                      hipStream_t s);
 
 // Shared by the single-lattice and batch entry points (pca_api.hip).
 int validate_params(const pca_params *p);     // PCA_OK or PCA_EINVAL with the error message set

@@ -124,6 +124,7 @@ int admit(pca_server *sv, Request *r, hipStream_t s)
     d.J = (double)p.J;
     d.q = (double)p.q;
     d.kappa = p.prior == PCA_PRIOR_POTTS ? 2.0 : 1.0;
+    d.inertia = p.inertia;
     d.sigma_s = (double)p.sigma * level_scale(p);
     d.key0 = (uint32_t)p.seed;
     d.key1 = (uint32_t)(p.seed >> 32);
@@ -298,10 +299,13 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     // 2. sweeps per request this step: at least one each, then the step's GPU-time budget
     //    goes to the requests with the least remaining work, so small requests finish in
     //    one step instead of being paced by the largest ones
+    // one launch runs one kernel: the requests sharing the oldest one's neighbourhood and
+    // inertia form advance now, the others in a later step
     const int nbr = sv->active.front()->p.neighbourhood;
+    const bool inr = sv->active.front()->p.inertia != 0;
     std::vector<Request *> cand;
     for (auto *r : sv->active)
-        if (r->p.neighbourhood == nbr) cand.push_back(r);  // other neighbourhoods: a later step
+        if (r->p.neighbourhood == nbr && (r->p.inertia != 0) == inr) cand.push_back(r);
     if (cand.size() < sv->active.size())
         std::rotate(sv->active.begin(), sv->active.begin() + 1, sv->active.end());
     std::map<Request *, int64_t> k;
@@ -395,7 +399,7 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         while (j > 0 && k[launched[j - 1]] <= i) --j;  // requests still advancing at launch i
         pcak::BatchLaunch bl{sv->d_desc, sv->d_block_img, (uint32_t)i};
-        e = pcak::launch_batch_sweep(bl, blocks_upto[j - 1], G, share, tiled, nbr, s);
+        e = pcak::launch_batch_sweep(bl, blocks_upto[j - 1], G, share, tiled, nbr, inr, s);
     }
     if (timed) (void)hipEventRecord(ev1, s);
     if (e != hipSuccess) return hip_fail(e, "server: sweep launch");

@@ -1,0 +1,554 @@
+// Device code shared by the gfx950 kernels of the lazy PCA sampler (Costarelli, Piconi, Troiani, arXiv 2507.14869,
+// Sec. 5.2).  The path is bound by vector ALU work (L level evaluations per site
+// update), so the kernels are written for VALU throughput: no MFMA (there is no dense
+// contraction), one thread per (pixel, group of up to four chains), chain-interleaved
+// uint8 state so one dword load brings a pixel's four chain values, the neighbour
+// statistic from byte-wise sums of absolute differences, and the per-sweep prior
+// factor table in LDS.
+//
+// Arithmetic of one site update (identical, operation for operation, to the written
+// convention the CPU reference follows; FP32, round to nearest even, no implicit
+// contraction - the file is built with -ffp-contract=off):
+//   exp2s(y)  = 0 if y < -125, else ldexp(p(f), n) with n = rint(y), f = y - n and p the
+//               degree-6 Taylor polynomial of 2^f (coefficients (float)(ln2^k / k!), the
+//               double values built as t_k = (t_{k-1} * ln2) / k), evaluated by fma Horner.
+//   D_k       = exp2s(fma(-a2, e_k*e_k, m)), e_k = g' - k, m = a2*(e0*e0), e0 = g' - khat,
+//               khat = clamp(rint(g'), 0, L-1), a2 = (float)(log2e / ((2 s) s)), s = sigma
+//               in level units: the Gaussian data term of Sec. 4, not scaled by beta.
+//   P(S)      = exp2s(-(c2 * S)), c2 = (float)(((beta*J)*kappa)*log2e), S = sum over
+//               in-lattice neighbours of min(|k - x_j|, T): the pair prior (Potts counts
+//               disagreeing neighbours with kappa = 2, T = 1).
+//   R         = exp2s((float)((beta*q)*log2e)) - 1: the inertia of Sec. 5.2 written as an
+//               extra "stay" weight, P(k|x) ~ D_k P(S_k) + [k = x] D_x P(S_x) R.
+//   acc_{-1}  = (D_x * P(S_x)) * R, acc_k = fma(D_k, P(S_k), acc_{k-1}), Z = acc_{L-1}.
+//   draw      = x if acc_{-1} > u Z, else the least k with acc_k > u Z (exact comparison,
+//               done as acc > RD(u Z)); x if Z == 0.  u = (r >> 8) 2^-24, r the chain's
+//               Philox4x32-10 word for counter {pixel, t, chain/4, 0}.
+// Inertia q|k - x|^p with p = 1 or 2 (Sec. 3, "The lazy PCA"; the L1/L2 norms of Sec. 5.2)
+// replaces the stay weight by one exponent per (chain, level) that holds both the data
+// and the inertia term, shifted by its maximum over the levels:
+//   F_k = fma(-a2, e_k*e_k, -(q2 * d^p)), d = |k - x|, q2 = (float)((beta*q)*log2e),
+//   acc_{-1} = 0, acc_k = fma(exp2s(F_k - Fmax), P(S_k), acc_{k-1}),
+//   Fmax = max(F_k1, F_k2), k1 = clamp(floor(kc), 0, L-1), k2 = min(k1+1, L-1), kc the
+//   real maximiser: clamp(x, g' - h, g' + h) with h = q2/(2 a2) for p = 1,
+//   (a2 g' + q2 x)/(a2 + q2) for p = 2.
+#pragma once
+
+#include "pca_internal.h"
+
+namespace pcak {
+namespace {
+
+
+// ---------------------------------------------------------------- exp2s
+
+constexpr double taylor_coeff(int k)
+{
+    double t = 1.0;
+    for (int i = 1; i <= k; ++i) t = (t * kLn2) / (double)i;
+    return t;
+}
+
+constexpr float kP0 = (float)taylor_coeff(0);
+constexpr float kP1 = (float)taylor_coeff(1);
+constexpr float kP2 = (float)taylor_coeff(2);
+constexpr float kP3 = (float)taylor_coeff(3);
+constexpr float kP4 = (float)taylor_coeff(4);
+constexpr float kP5 = (float)taylor_coeff(5);
+constexpr float kP6 = (float)taylor_coeff(6);
+
+__device__ __forceinline__ float exp2s(float y)
+{
+    const float n = __builtin_rintf(y);
+    const float f = y - n;
+    float p = kP6;
+    p = __builtin_fmaf(p, f, kP5);
+    p = __builtin_fmaf(p, f, kP4);
+    p = __builtin_fmaf(p, f, kP3);
+    p = __builtin_fmaf(p, f, kP2);
+    p = __builtin_fmaf(p, f, kP1);
+    p = __builtin_fmaf(p, f, kP0);
+    const float r = __builtin_amdgcn_ldexpf(p, (int)n);
+    return y < -125.0f ? 0.0f : r;
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+__device__ __forceinline__ uint32_t word_of(const U4 &r, int i)
+{
+    return i == 0 ? r.x : i == 1 ? r.y : i == 2 ? r.z : r.w;
+}
+
+// Round-down of the exact product u*Z (both FP32, exact in double).
+__device__ __forceinline__ float threshold_rd(float u, float Z)
+{
+    const double t = (double)u * (double)Z;
+    float f = (float)t;
+    if ((double)f > t) f = __uint_as_float(__float_as_uint(f) - 1u);  // f > t >= 0
+    return f;
+}
+
+template <int G>
+__device__ __forceinline__ uint32_t load_group(const uint8_t *p)
+{
+    if constexpr (G == 4) return *reinterpret_cast<const uint32_t *>(p);
+    else if constexpr (G == 2) return *reinterpret_cast<const uint16_t *>(p);
+    else return *p;
+}
+
+template <int G>
+__device__ __forceinline__ void store_group(uint8_t *p, uint32_t v)
+{
+    if constexpr (G == 4) *reinterpret_cast<uint32_t *>(p) = v;
+    else if constexpr (G == 2) *reinterpret_cast<uint16_t *>(p) = (uint16_t)v;
+    else *p = (uint8_t)v;
+}
+
+// ---------------------------------------------------------------- sweep
+
+// Per-chain neighbour data for the byte-wise statistic.  With lo_j = max(x_j - T_j, 0),
+// hi_j = min(x_j + T_j, 255) and T_j = 0 for absent neighbours, for every k in [0, 255]
+//   2 min(|k - x_j|, T_j) = 2|k - x_j| - |k - hi_j| - |k - lo_j| + (hi_j - lo_j),
+// so 2S_k = 2 SAD(k, x) - SAD(k, hi) - SAD(k, lo) + sum_j (hi_j - lo_j), each SAD one
+// v_sad_u8 over four neighbours packed in a dword.
+template <int NW>
+struct NbrPack {
+    uint32_t x[NW], lo[NW], hi[NW];
+    int cb;  // 2 * sum_j (hi_j - lo_j): byte offset term of the table address
+};
+
+template <int NW>
+__device__ __forceinline__ float prior_lookup(const char *ptab, const NbrPack<NW> &nb, uint32_t kk)
+{
+    uint32_t u = 0, v = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        u = __builtin_amdgcn_sad_u8(kk, nb.x[w], u);
+        v = __builtin_amdgcn_sad_u8(kk, nb.lo[w], v);
+        v = __builtin_amdgcn_sad_u8(kk, nb.hi[w], v);
+    }
+    // byte offset 4 S = 4u - 2v + 2 sum(hi - lo), as one shift-add and one 24-bit mad
+    int off;
+    asm("v_lshl_add_u32 %0, %1, 2, %2\n\tv_mad_i32_i24 %0, %3, -2, %0" : "=&v"(off) : "v"(u), "v"(nb.cb), "v"(v));
+    return *reinterpret_cast<const float *>(ptab + off);
+}
+
+// Broadcast lane J of each group of SHARE consecutive lanes to the whole group (DPP
+// quad permutation; groups never straddle a quad).
+template <int SHARE, int J>
+__device__ __forceinline__ float group_bcast(float v)
+{
+    if constexpr (SHARE == 1) {
+        return v;
+    } else {
+        constexpr int ctrl = SHARE == 4 ? (J | (J << 2) | (J << 4) | (J << 6))
+                                        : (J | (J << 2) | ((2 + J) << 4) | ((2 + J) << 6));
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), ctrl, 0xF, 0xF, false));
+    }
+}
+
+template <int G, int NW>
+__device__ __forceinline__ void level_update(const char *pt, const NbrPack<NW> (&nb)[G], float (&acc)[G], float D,
+                                             uint32_t kk)
+{
+#pragma unroll
+    for (int ch = 0; ch < G; ++ch) acc[ch] = __builtin_fmaf(D, prior_lookup<NW>(pt, nb[ch], kk), acc[ch]);
+}
+
+// Levels J.. of a group of SHARE consecutive levels; only the first nlev exist.
+template <int SHARE, int J, int G, int NW>
+__device__ __forceinline__ void group_levels(const char *pt, const NbrPack<NW> (&nb)[G], float (&acc)[G], float Dmine,
+                                             uint32_t &kk, int nlev)
+{
+    if constexpr (J < SHARE) {
+        if (J < nlev) {
+            level_update<G, NW>(pt, nb, acc, group_bcast<SHARE, J>(Dmine), kk);
+            kk += 0x01010101u;
+            group_levels<SHARE, J + 1, G, NW>(pt, nb, acc, Dmine, kk, nlev);
+        }
+    }
+}
+
+// All SHARE levels of a group.
+template <int SHARE, int J, int G, int NW>
+__device__ __forceinline__ void group_full(const char *pt, const NbrPack<NW> (&nb)[G], float (&acc)[G], float Dmine,
+                                           uint32_t &kk)
+{
+    if constexpr (J < SHARE) {
+        level_update<G, NW>(pt, nb, acc, group_bcast<SHARE, J>(Dmine), kk);
+        kk += 0x01010101u;
+        group_full<SHARE, J + 1, G, NW>(pt, nb, acc, Dmine, kk);
+    }
+}
+
+// Per-sweep scalars shared by a workgroup, and the prior factor table P(S), S = 0..nbr*T,
+// in LDS.  Every thread of the workgroup must call this (it ends with a barrier).
+struct SweepConsts {
+    float R, a2, q2;
+};
+
+__device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nbr, float *ptab)
+{
+    const float c2 = (float)(((a.beta * a.J) * a.kappa) * kLog2e);
+    const float q2 = (float)((a.beta * a.q) * kLog2e);
+    SweepConsts k;
+    k.R = exp2s(q2) - 1.0f;
+    k.q2 = q2;
+    k.a2 = (float)(kLog2e / ((2.0 * a.sigma_s) * a.sigma_s));
+    const int nP = nbr * a.T + 1;
+    for (int s = threadIdx.x; s < nP; s += blockDim.x) ptab[s] = exp2s(-(c2 * (float)s));
+    __syncthreads();
+    return k;
+}
+
+// Exponent F_k of the L1/L2 inertia form: data term plus q2 |k - x|^p (log2 units).
+__device__ __forceinline__ float inertia_exponent(float ee, int k, int x, int p, float a2, float q2)
+{
+    const int d = k > x ? k - x : x - k;
+    const int dp = p == 1 ? d : d * d;
+    return __builtin_fmaf(-a2, ee, -(q2 * (float)dp));
+}
+
+// Maximum of F_k over the levels: F is concave in k, so it is attained next to the
+// maximiser kc of the real-valued form.
+__device__ __forceinline__ float inertia_fmax(float gp, int x, int L, int p, float a2, float q2)
+{
+    float kc;
+    if (p == 1) {
+        const float h = q2 / (2.0f * a2);
+        kc = fminf(fmaxf((float)x, gp - h), gp + h);
+    } else {
+        kc = (a2 * gp + q2 * (float)x) / (a2 + q2);
+    }
+    const int k1 = (int)fminf(fmaxf(floorf(kc), 0.0f), (float)(L - 1));
+    const int k2 = k1 + 1 < L ? k1 + 1 : k1;
+    const float e1 = gp - (float)k1, e2 = gp - (float)k2;
+    const float F1 = inertia_exponent(e1 * e1, k1, x, p, a2, q2);
+    const float F2 = inertia_exponent(e2 * e2, k2, x, p, a2, q2);
+    return F1 > F2 ? F1 : F2;
+}
+
+// One thread's site updates: pixel (r, c) = pix, chains grp*G .. grp*G+G-1.  `q` is the
+// thread's position in its group of SHARE lanes serving the same pixel.
+// INR selects the L1/L2 inertia form (a.inertia = 1 or 2; SHARE must then be 1).
+template <int G, int NBR, int SUB, int NBLK, int SHARE, bool INR = false>
+__device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab, SweepConsts kc, int pix, int r,
+                                           int c, int grp, int q)
+{
+    constexpr int NW = NBR / 4;
+    const float R = kc.R;
+    const float a2 = kc.a2;
+    const int tpp = a.Cp / G;
+    const int cofs = grp * G;
+    const int L = a.L;
+
+    // Observation and the data-term shift.
+    const float gp = a.gp[pix];
+    float khat = __builtin_rintf(gp);
+    khat = khat < 0.0f ? 0.0f : khat;
+    khat = khat > (float)(L - 1) ? (float)(L - 1) : khat;
+    const float e0 = gp - khat;
+    const float m = a2 * (e0 * e0);
+
+    // State words of the pixel and its neighbours (G chains each).
+    const uint8_t *xin = a.xin;
+    const uint32_t own = load_group<G>(xin + (int64_t)pix * a.Cp + cofs);
+    uint32_t nbw[NBR];
+    bool present[NBR];
+    {
+        const int dr[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
+        const int dc[8] = {0, 0, -1, 1, -1, 1, -1, 1};
+#pragma unroll
+        for (int j = 0; j < NBR; ++j) {
+            const int rr = r + dr[j], cc = c + dc[j];
+            present[j] = rr >= 0 && rr < a.H && cc >= 0 && cc < a.W;
+            nbw[j] = present[j] ? load_group<G>(xin + ((int64_t)rr * a.W + cc) * a.Cp + cofs) : 0u;
+        }
+    }
+
+    const char *pt = reinterpret_cast<const char *>(ptab);
+    NbrPack<NW> nb[G];
+    int xs[G];
+    float stay[G], acc[G], fmx[G];
+#pragma unroll
+    for (int ch = 0; ch < G; ++ch) {
+        xs[ch] = (int)((own >> (8 * ch)) & 0xFFu);
+        int csum = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            nb[ch].x[w] = nb[ch].lo[w] = nb[ch].hi[w] = 0u;
+        }
+#pragma unroll
+        for (int j = 0; j < NBR; ++j) {
+            const int xj = (int)((nbw[j] >> (8 * ch)) & 0xFFu);
+            const int Tj = present[j] ? a.T : 0;
+            const int lo = xj > Tj ? xj - Tj : 0;
+            const int hi = xj + Tj < 255 ? xj + Tj : 255;
+            csum += hi - lo;
+            nb[ch].x[j / 4] |= (uint32_t)xj << (8 * (j % 4));
+            nb[ch].lo[j / 4] |= (uint32_t)lo << (8 * (j % 4));
+            nb[ch].hi[j / 4] |= (uint32_t)hi << (8 * (j % 4));
+        }
+        nb[ch].cb = 2 * csum;
+        if constexpr (INR) {
+            fmx[ch] = inertia_fmax(gp, xs[ch], L, a.inertia, a2, kc.q2);
+            stay[ch] = 0.0f;
+        } else {
+            // Stay weight of the lazy conditional.
+            const float ex = gp - (float)xs[ch];
+            const float Dx = exp2s(__builtin_fmaf(-a2, ex * ex, m));
+            const float Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)xs[ch] * 0x01010101u);
+            stay[ch] = (Dx * Px) * R;
+        }
+        acc[ch] = stay[ch];
+    }
+
+    // Main pass over levels, keeping the running sum at the end of every block.  The
+    // SHARE lanes serving one pixel each compute the data factor of every SHARE-th level
+    // and broadcast it, so a pixel's chains share one evaluation per level.
+    float part[NBLK][G];
+    const int nblk = (L + SUB - 1) / SUB;
+    uint32_t kk = 0u;
+    float kq = (float)q;  // level whose data factor this lane evaluates next
+    if constexpr (INR) {
+        // L1/L2 inertia: every (chain, level) has its own exponent; nothing is shared.
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            if (b < nblk) {
+                const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
+                for (int i = 0; i < kend; ++i) {
+                    const int k = b * SUB + i;
+                    const float e = gp - (float)k;
+                    const float ee = e * e;
+#pragma unroll
+                    for (int ch = 0; ch < G; ++ch) {
+                        const float E = exp2s(inertia_exponent(ee, k, xs[ch], a.inertia, a2, kc.q2) - fmx[ch]);
+                        acc[ch] = __builtin_fmaf(E, prior_lookup<NW>(pt, nb[ch], kk), acc[ch]);
+                    }
+                    kk += 0x01010101u;
+                }
+#pragma unroll
+                for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
+            }
+        }
+    } else if constexpr (SUB == 1) {
+#pragma unroll
+        for (int k0 = 0; k0 < NBLK; k0 += SHARE) {
+            if (k0 < L) {
+                const float e = gp - kq;
+                const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                kq += (float)SHARE;
+#pragma unroll
+                for (int j = 0; j < SHARE; ++j) {
+                    if (k0 + j < L) {
+                        float D;
+                        if (j == 0) D = group_bcast<SHARE, 0>(Dm);
+                        else if (j == 1) D = group_bcast<SHARE, (SHARE > 1 ? 1 : 0)>(Dm);
+                        else if (j == 2) D = group_bcast<SHARE, (SHARE > 2 ? 2 : 0)>(Dm);
+                        else D = group_bcast<SHARE, (SHARE > 3 ? 3 : 0)>(Dm);
+                        level_update<G, NW>(pt, nb, acc, D, kk);
+                        kk += 0x01010101u;
+#pragma unroll
+                        for (int ch = 0; ch < G; ++ch) part[k0 + j][ch] = acc[ch];
+                    }
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NBLK; ++b) {
+            if (b < nblk) {
+                const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
+                if (kend == SUB) {
+#pragma unroll 2
+                    for (int i = 0; i < SUB; i += SHARE) {
+                        const float e = gp - kq;
+                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        kq += (float)SHARE;
+                        group_full<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk);
+                    }
+                } else {
+                    for (int i = 0; i < kend; i += SHARE) {
+                        const float e = gp - kq;
+                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        kq += (float)SHARE;
+                        group_levels<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk, kend - i);
+                    }
+                }
+#pragma unroll
+                for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
+            }
+        }
+    }
+
+    // Inverse-CDF draw for each chain.
+    const int chain0 = cofs;
+    const U4 rnd = philox(U4{(uint32_t)pix, a.t, (uint32_t)(chain0 >> 2), 0u}, a.key0, a.key1);
+    uint32_t packed = 0u;
+    uint32_t lsum = 0u;
+    int knew[G];
+#pragma unroll
+    for (int ch = 0; ch < G; ++ch) {
+        const uint32_t w = word_of(rnd, (chain0 & 3) + ch);
+        const float u = (float)(w >> 8) * 0x1p-24f;
+        const float Z = acc[ch];
+        int k = xs[ch];
+        if (Z != 0.0f) {
+            const float tf = threshold_rd(u, Z);
+            if (!(stay[ch] > tf)) {
+                int bsel = nblk - 1;
+                float start = 0.0f;
+#pragma unroll
+                for (int b = NBLK - 1; b >= 0; --b) {
+                    if (b < nblk && part[b][ch] > tf) {
+                        bsel = b;
+                        start = b == 0 ? stay[ch] : part[b > 0 ? b - 1 : 0][ch];
+                    }
+                }
+                if constexpr (SUB == 1) {
+                    k = bsel;
+                } else {
+                    // Re-run the sums of the selected block; they reproduce the main pass exactly.
+                    const int k0 = bsel * SUB;
+                    const int kend = (L - k0) < SUB ? (L - k0) : SUB;
+                    float s = start;
+                    k = k0 + kend - 1;
+                    uint32_t kk2 = (uint32_t)k0 * 0x01010101u;
+                    for (int i = 0; i < kend; ++i) {
+                        float D;
+                        if constexpr (INR) {
+                            const float e = gp - (float)(k0 + i);
+                            D = exp2s(inertia_exponent(e * e, k0 + i, xs[ch], a.inertia, a2, kc.q2) - fmx[ch]);
+                        } else {
+                            const float e = gp - (float)(k0 + i);
+                            D = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        }
+                        const float P = prior_lookup<NW>(pt, nb[ch], kk2);
+                        s = __builtin_fmaf(D, P, s);
+                        if (s > tf) {
+                            k = k0 + i;
+                            break;
+                        }
+                        kk2 += 0x01010101u;
+                    }
+                }
+            }
+        }
+        knew[ch] = k;
+        packed |= (uint32_t)k << (8 * ch);
+        if (chain0 + ch < a.C) lsum += (uint32_t)k;
+    }
+    store_group<G>(a.xout + (int64_t)pix * a.Cp + cofs, packed);
+
+    if (a.sum) {
+        // Lanes of a pixel sit in aligned pairs or quads when tpp is 2 or 4: add their sums
+        // with DPP and let the first lane update the word, instead of one atomic per lane
+        // (global atomics are performed past L2, one memory write each).
+        if (tpp == 1) {
+            a.sum[pix] += lsum;
+        } else if (tpp == 2 || tpp == 4) {
+            uint32_t s = lsum + (uint32_t)__builtin_amdgcn_mov_dpp((int)lsum, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+            if (tpp == 4) s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);      // [2,3,0,1]
+            if (grp == 0) a.sum[pix] += s;
+        } else {
+            atomicAdd(a.sum + pix, lsum);
+        }
+    }
+    if (a.hist) {
+        uint32_t *hrow = a.hist + (int64_t)pix * a.hist_words;
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch) {
+            if (chain0 + ch < a.C) atomicAdd(hrow + (knew[ch] >> 1), 1u << (16 * (knew[ch] & 1)));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- batched sweep
+
+// One sweep of every lattice of a batch in one launch.  Each workgroup belongs to one
+// lattice (its descriptor is read once, uniformly); lattices may differ in size, level
+// count, chains, parameters, seed and sweep index.  The sweep index lives in the
+// descriptor in device memory, so a captured graph of n launches can be replayed for the
+// next n sweeps; a lattice whose index reached its end is skipped.
+template <int G, int SHARE, int TILED, int NBR, bool INR = false>
+__global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
+{
+    __shared__ float ptab[kMaxNeighbourStat + 1];
+    const int img = b.block_img[blockIdx.x];
+    const ImageDesc &d = b.imgs[img];
+    const uint32_t t = d.t + b.toff;
+    if (t >= d.t_end) return;  // this lattice has finished (uniform over the workgroup)
+    SweepArgs a;
+    a.gp = d.gp;
+    a.xin = (t & 1u) ? d.x1 : d.x0;
+    a.xout = (t & 1u) ? d.x0 : d.x1;
+    const bool acc = (int64_t)t >= d.burn_in;
+    const bool tally = acc && d.tally_stride > 0 && ((int64_t)t - d.burn_in) % d.tally_stride == 0;
+    a.sum = acc ? d.sum : nullptr;
+    a.hist = tally ? d.hist : nullptr;
+    a.H = d.H;
+    a.W = d.W;
+    a.L = d.L;
+    a.C = d.C;
+    a.Cp = d.Cp;
+    a.T = d.T;
+    a.hist_words = d.hist_words;
+    a.beta = d.beta_len == 0 ? 1.0 : d.beta[(int)t < d.beta_len ? (int)t : d.beta_len - 1];
+    a.J = d.J;
+    a.q = d.q;
+    a.kappa = d.kappa;
+    a.sigma_s = d.sigma_s;
+    a.key0 = d.key0;
+    a.key1 = d.key1;
+    a.t = t;
+    a.inertia = d.inertia;
+    const SweepConsts kc = sweep_prologue(a, NBR, ptab);
+
+    const int tpp = d.tpp;
+    const int local = (int)blockIdx.x - d.block_base;
+    int pix, r, c, grp;
+    if constexpr (TILED == 0) {
+        const int64_t gid = (int64_t)local * kBlock + threadIdx.x;
+        if (gid >= (int64_t)d.H * d.W * tpp) return;
+        pix = (int)(gid / tpp);
+        grp = (int)(gid - (int64_t)pix * tpp);
+        r = pix / d.W;
+        c = pix - r * d.W;
+    } else {
+        const int th = kBlock / tpp / kTileW;  // tile height in pixels
+        const int tr = local / d.tiles_w, tc = local - (local / d.tiles_w) * d.tiles_w;
+        const int lp = (int)threadIdx.x / tpp;
+        grp = (int)threadIdx.x - lp * tpp;
+        r = tr * th + lp / kTileW;
+        c = tc * kTileW + lp % kTileW;
+        if (r >= d.H || c >= d.W) return;
+        pix = r * d.W + c;
+    }
+    const int q = (int)(threadIdx.x % SHARE);
+    if (a.L <= 16) sweep_site<G, NBR, 1, 16, SHARE, INR>(a, ptab, kc, pix, r, c, grp, q);
+    else sweep_site<G, NBR, 16, 16, SHARE, INR>(a, ptab, kc, pix, r, c, grp, q);
+}
+
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+}  // namespace
+}  // namespace pcak

@@ -16,7 +16,7 @@ def torch_cuda():
 
 def params_dict(**kw):
     keys = ("height", "width", "levels", "chains", "neighbourhood", "prior", "trunc", "J", "q", "sigma", "vmin",
-            "vmax", "beta", "seed", "init_mode", "burn_in", "tally_stride")
+            "vmax", "beta", "seed", "init_mode", "burn_in", "tally_stride", "inertia")
     return {k: v for k, v in kw.items() if k in keys}
 
 

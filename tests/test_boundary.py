@@ -59,7 +59,8 @@ def test_null_context_is_rejected(lib):
                                  dict(neighbourhood=6), dict(prior=2), dict(trunc=0), dict(J=-0.1), dict(q=-1.0),
                                  dict(sigma=0.0), dict(vmax=0.0), dict(init_mode=2), dict(burn_in=-1),
                                  dict(tally_stride=-1), dict(beta=[1.0, -2.0]), dict(height=0),
-                                 dict(J=float("nan")), dict(q=80.0), dict(width=70000, height=70000)])
+                                 dict(J=float("nan")), dict(q=80.0), dict(width=70000, height=70000),
+                                 dict(inertia=3), dict(inertia=-1)])
 def test_invalid_parameters_are_rejected_without_a_device(lib, bad):
     from paper_2507_14869_amd import _lib
     kw = dict(height=4, width=4, levels=4, chains=1, J=0.1, q=0.5, sigma=1.0)

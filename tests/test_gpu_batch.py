@@ -117,3 +117,24 @@ def test_batch_eight_neighbour():
     for i, (obs, kw) in enumerate(problems):
         ref = _alone(obs, kw, 7)
         assert np.array_equal(b.state(i).cpu().numpy(), ref.state().cpu().numpy()), i
+
+
+def test_batch_with_inertia_norms(orc):
+    """Lattices with L1 and L2 inertia in one batch (their kernel differs from the
+    indicator's, so a batch holds one form or the other)."""
+    problems = [_problem(33, 20, 256, 4, 31, inertia=1, q=0.02), _problem(40, 17, 16, 4, 32, inertia=2, q=0.3),
+                _problem(19, 25, 2, 2, 33, inertia=1), _problem(12, 70, 33, 8, 34, inertia=2, q=0.05)]
+    b = _batch(problems)
+    assert b.config[1] == 1
+    b.sweep(3).sweep(3)
+    for i, (obs, kw) in enumerate(problems):
+        ref = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(6)
+        assert np.array_equal(b.state(i).cpu().numpy(), ref.state), i
+        assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean())
+        assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map())
+    from paper_2507_14869_amd import PcaError
+    with pytest.raises(PcaError):
+        b.set_config(4, 2, 0)
+    with pytest.raises(PcaError):
+        _batch([problems[0], _problem(16, 16, 16, 4, 35)])
+    b.close()

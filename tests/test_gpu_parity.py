@@ -93,6 +93,64 @@ def test_value_units_and_random_init(orc):
     assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
 
 
+@pytest.mark.parametrize("case", [
+    # (L, chains, tally stride, sweeps per call, reset the state after call i)
+    (33, 5, 1, (3, 9, 1, 20), 1),
+    (33, 5, 2, (5, 17, 4), None),
+    (256, 16, 3, (8, 8, 8), 0),
+    (16, 8, 5, (30,), None),
+    (2, 2, 9, (7, 13, 11, 40), 2),
+])
+def test_deferred_tallies_match_oracle(orc, case):
+    """Tally sweeps are folded into the histogram in bursts; the mode read between calls,
+    after a state reset or at any sweep count must still count every tally sweep once."""
+    torch = torch_cuda()
+    L, C, stride, calls, reset_after = case
+    H, W = 21, 34
+    obs = _obs(H, W, L, seed=L + C + stride, sigma=0.25 * L)
+    kw = dict(height=H, width=W, levels=L, chains=C, prior=1 if L > 2 else 0, trunc=max(1, L // 8), J=0.3,
+              q=1.2, sigma=0.25 * L, vmin=0.0, vmax=float(L - 1), seed=77 + stride, burn_in=2, tally_stride=stride)
+    ref = oracle_run(orc, obs, **kw)
+    gpu = gpu_sampler(obs, **kw)
+    for i, n in enumerate(calls):
+        ref.sweep(n)
+        gpu.sweep(n)
+        tallies = len(range(2, ref.t, stride))
+        assert gpu.stats() == (ref.t, int(ref.count[0]), tallies)
+        assert np.array_equal(gpu.state().cpu().numpy(), ref.state), i
+        if tallies > 0 and i % 2 == 0:
+            assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map()), i
+        if i == reset_after:  # a state write must not lose the pending tallies
+            gpu.set_state(torch.from_numpy(ref.state.copy()).cuda(), ref.t)
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+
+
+@pytest.mark.parametrize("case", [
+    # (H, W, L, chains, nbr, prior, T, J, q, sigma, inertia exponent)
+    (37, 41, 256, 16, 4, 1, 32, 0.05, 0.02, 20.0, 1),  # c3-shaped, L1 inertia
+    (37, 41, 256, 16, 4, 1, 32, 0.05, 0.002, 20.0, 2),  # c3-shaped, L2 inertia
+    (40, 33, 16, 8, 4, 1, 4, 0.4, 0.4, 2.0, 1),       # c2-shaped, one block per level
+    (29, 31, 33, 3, 8, 1, 3, 0.3, 0.2, 3.0, 2),       # padded chains, 8 neighbours
+    (21, 18, 5, 1, 8, 0, 1, 1 / 3, 0.5, 0.6, 2),      # paper-like Potts, one chain
+    (16, 19, 200, 2, 4, 1, 9, 0.1, 3.0, 1.0, 2),      # inertia far stronger than the data
+])
+def test_inertia_norm_stepwise_parity(orc, case):
+    """The L1 and L2 inertia forms: same per-site arithmetic as the CPU reference."""
+    H, W, L, C, nbr, prior, T, J, q, sigma, p = case
+    obs = _obs(H, W, L, seed=H * 1000 + W + p, sigma=sigma)
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=nbr, prior=prior, trunc=T, J=J, q=q,
+              sigma=sigma, vmin=0.0, vmax=float(L - 1), beta=[1.25, 1.5, 2.0], seed=5151 + H, burn_in=1,
+              tally_stride=1, inertia=p, init_mode=1)
+    bad, total, ref, gpu = stepwise(orc, obs, 5, **kw)
+    assert bad <= FLIP_BUDGET * total, f"{bad} of {total} site updates differ"
+    ref2 = oracle_run(orc, obs, **kw).sweep(12)
+    gpu2 = gpu_sampler(obs, **kw).sweep(12)
+    assert np.array_equal(gpu2.state().cpu().numpy(), ref2.state)
+    assert np.array_equal(gpu2.posterior_mean().cpu().numpy(), ref2.posterior_mean())
+    assert np.array_equal(gpu2.marginal_map().cpu().numpy(), ref2.marginal_map())
+
+
 def test_sweep_splitting_is_invisible(orc):
     wl = synth.make_workload("c2", height=64, width=48, chains=8)
     kw = wl.params(beta=[1.0, 1.5, 2.0], burn_in=2)

@@ -121,3 +121,29 @@ def test_server_rejects_bad_requests():
     while sv.status(rid)[0] != 2:
         sv.step()
     sv.close()
+
+
+def test_requests_with_different_kernels_share_the_server():
+    """Requests needing different kernels (4 or 8 neighbours, indicator or L2 inertia)
+    are served in the same steps' rotation and each equals its run alone."""
+    sv = _server(budget=1 << 34, k=4, step_ms=0.5)
+    specs = [((30, 31, 16, 2, 41), {}), ((22, 40, 33, 2, 42), dict(inertia=2, q=0.1)),
+             ((25, 25, 5, 2, 43), dict(neighbourhood=8, prior=0, trunc=1)),
+             ((18, 33, 256, 2, 44), dict(inertia=1, q=0.02))]
+    reqs = {}
+    for spec, over in specs:
+        obs, kw = _problem(*spec, **over)
+        reqs[sv.submit(obs, 9, **kw)] = (obs, kw)
+    done = set()
+    for _ in range(200):
+        sv.step()
+        done.update(sv.completed())
+        if len(done) == len(reqs):
+            break
+    assert done == set(reqs)
+    for rid, (obs, kw) in reqs.items():
+        mean, mpm, state = sv.result(rid)
+        ref = _alone(obs, kw, 9)
+        assert np.array_equal(state, ref[2]), rid
+        assert np.array_equal(mean, ref[0]) and np.array_equal(mpm, ref[1]), rid
+    sv.close()
