@@ -200,6 +200,19 @@ __device__ __forceinline__ void group_full(const char *pt, const NbrPack<NW> (&n
     }
 }
 
+// Levels J.. of a group of SHARE consecutive levels where every chain's neighbour
+// statistic is at its maximum: the prior factor is the same table entry for all of them.
+template <int SHARE, int J, int G>
+__device__ __forceinline__ void group_far(float (&acc)[G], float Dmine, float pfar)
+{
+    if constexpr (J < SHARE) {
+        const float D = group_bcast<SHARE, J>(Dmine);
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch) acc[ch] = __builtin_fmaf(D, pfar, acc[ch]);
+        group_far<SHARE, J + 1, G>(acc, Dmine, pfar);
+    }
+}
+
 // Per-sweep scalars shared by a workgroup, and the prior factor table P(S), S = 0..nbr*T,
 // in LDS.  Every thread of the workgroup must call this (it ends with a barrier).
 struct SweepConsts {
@@ -289,6 +302,11 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
     NbrPack<NW> nb[G];
     int xs[G];
     float stay[G], acc[G], fmx[G];
+    // Levels outside [nlo, nhi] are at least T away from every present neighbour of every
+    // chain of this thread, so their statistic is npres*T.
+    int nlo = 1 << 20, nhi = -(1 << 20), npres = 0;
+#pragma unroll
+    for (int j = 0; j < NBR; ++j) npres += present[j] ? 1 : 0;
 #pragma unroll
     for (int ch = 0; ch < G; ++ch) {
         xs[ch] = (int)((own >> (8 * ch)) & 0xFFu);
@@ -304,6 +322,10 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
             const int lo = xj > Tj ? xj - Tj : 0;
             const int hi = xj + Tj < 255 ? xj + Tj : 255;
             csum += hi - lo;
+            if (present[j]) {
+                nlo = xj - a.T + 1 < nlo ? xj - a.T + 1 : nlo;
+                nhi = xj + a.T - 1 > nhi ? xj + a.T - 1 : nhi;
+            }
             nb[ch].x[j / 4] |= (uint32_t)xj << (8 * (j % 4));
             nb[ch].lo[j / 4] |= (uint32_t)lo << (8 * (j % 4));
             nb[ch].hi[j / 4] |= (uint32_t)hi << (8 * (j % 4));
@@ -378,7 +400,19 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         for (int b = 0; b < NBLK; ++b) {
             if (b < nblk) {
                 const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
-                if (kend == SUB) {
+                const bool lane_far = b * SUB + SUB - 1 < nlo || b * SUB > nhi;
+                if (kend == SUB && __all(lane_far)) {
+                    // the whole wave is far from its neighbours' levels in this block
+                    const float pfar = ptab[npres * a.T];
+#pragma unroll 2
+                    for (int i = 0; i < SUB; i += SHARE) {
+                        const float e = gp - kq;
+                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        kq += (float)SHARE;
+                        group_far<SHARE, 0, G>(acc, Dm, pfar);
+                    }
+                    kk += (uint32_t)SUB * 0x01010101u;
+                } else if (kend == SUB) {
 #pragma unroll 2
                     for (int i = 0; i < SUB; i += SHARE) {
                         const float e = gp - kq;

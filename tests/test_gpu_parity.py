@@ -151,6 +151,24 @@ def test_inertia_norm_stepwise_parity(orc, case):
     assert np.array_equal(gpu2.marginal_map().cpu().numpy(), ref2.marginal_map())
 
 
+@pytest.mark.parametrize("C", [12, 32, 100, 1024])
+def test_many_chains_per_pixel(orc, C):
+    """Chain counts whose lanes per pixel (chains / 4) are 3, 8, 25 and 256: pixels whose
+    lanes do not fill a quad, span several quads, or several waves.  The mean accumulator
+    then takes the per-lane atomic path instead of the quad reduction."""
+    H, W, L = 9, 7, 33 if C < 1024 else 5
+    obs = _obs(H, W, L, seed=C)
+    kw = dict(height=H, width=W, levels=L, chains=C, prior=1, trunc=4, J=0.3, q=0.9, sigma=0.2 * L, vmin=0.0,
+              vmax=float(L - 1), beta=[1.2, 1.6], seed=31 + C, burn_in=1, tally_stride=1,
+              init_mode=1)
+    n = 6 if C < 1024 else 3
+    ref = oracle_run(orc, obs, **kw).sweep(n)
+    gpu = gpu_sampler(obs, **kw).sweep(n)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+
+
 def test_sweep_splitting_is_invisible(orc):
     wl = synth.make_workload("c2", height=64, width=48, chains=8)
     kw = wl.params(beta=[1.0, 1.5, 2.0], burn_in=2)
