@@ -509,9 +509,41 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
     }
     if (a.hist) {
         uint32_t *hrow = a.hist + (int64_t)pix * a.hist_words;
+        if (SUB == 1 && (tpp == 1 || tpp == 2 || tpp == 4)) {
+            // L <= 16: the pixel's whole counter row (at most 8 words) is built in registers,
+            // summed across the pixel's lanes with DPP and added to memory by plain
+            // read-modify-writes, one word per lane: no global atomics, which are performed
+            // beyond the L2 here and would dominate a sweep with so few levels.
+            const int nw = a.hist_words;
+            uint32_t row[8];
 #pragma unroll
-        for (int ch = 0; ch < G; ++ch) {
-            if (chain0 + ch < a.C) atomicAdd(hrow + (knew[ch] >> 1), 1u << (16 * (knew[ch] & 1)));
+            for (int w = 0; w < 8; ++w) row[w] = 0u;
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) {
+                const int wi = chain0 + ch < a.C ? knew[ch] >> 1 : -1;
+                const uint32_t inc = (knew[ch] & 1) ? 0x10000u : 1u;
+#pragma unroll
+                for (int w = 0; w < 8; ++w)
+                    if (w < nw) row[w] += wi == w ? inc : 0u;
+            }
+            if (tpp >= 2) {
+#pragma unroll
+                for (int w = 0; w < 8; ++w)
+                    if (w < nw) row[w] += (uint32_t)__builtin_amdgcn_mov_dpp((int)row[w], 0xB1, 0xF, 0xF, false);
+            }
+            if (tpp == 4) {
+#pragma unroll
+                for (int w = 0; w < 8; ++w)
+                    if (w < nw) row[w] += (uint32_t)__builtin_amdgcn_mov_dpp((int)row[w], 0x4E, 0xF, 0xF, false);
+            }
+#pragma unroll
+            for (int w = 0; w < 8; ++w)
+                if (w < nw && (w & (tpp - 1)) == grp && row[w] != 0u) hrow[w] += row[w];
+        } else {
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) {
+                if (chain0 + ch < a.C) atomicAdd(hrow + (knew[ch] >> 1), 1u << (16 * (knew[ch] & 1)));
+            }
         }
     }
 }
