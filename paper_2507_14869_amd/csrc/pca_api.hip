@@ -1,6 +1,7 @@
 // C ABI of the lazy PCA sampler (declared in include/pca.h): parameter validation,
 // device memory, sweep bookkeeping (beta schedule, burn-in, tally sweeps) and error
-// reporting.  Every step of the sampler itself runs in the kernels of pca_kernels.hip.
+// reporting.  Every step of the sampler itself runs in the HIP kernels (pca_kernels*.hip,
+// per-site arithmetic in pca_sweep.h).
 #include <hip/hip_runtime.h>
 
 #include <cmath>

@@ -1,5 +1,6 @@
-// Internal interface between the C-ABI layer (pca_api.hip) and the gfx950 kernels
-// (pca_kernels.hip).  Not part of the public boundary; see include/pca.h.
+// Internal interface between the host side of the C ABI (pca_api.hip, pca_batch.hip,
+// pca_serve.hip) and the gfx950 kernels (pca_kernels*.hip, per-site code in pca_sweep.h).
+// Not part of the public boundary; see include/pca.h.
 #pragma once
 
 #include <hip/hip_runtime.h>
