@@ -115,6 +115,22 @@ int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream);
  * accumulated sweeps) and the number of tally sweeps.  Any pointer may be NULL. */
 int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *tallies);
 
+/* Checkpoint of the accumulators (with pca_get_state and pca_stats, everything a run needs
+ * to resume bit-exactly, since every draw is keyed by the sweep index and not by a
+ * generator state).  sum_dev: device uint32 [height][width], the sum of the levels of all
+ * chains over the accumulated sweeps; hist_dev: device uint16 [height][width][levels], the
+ * tally of each level over chains and tally sweeps, or NULL (required to be NULL when the
+ * histogram is disabled).  Errors: PCA_EINVAL. */
+int pca_get_accumulators(pca_ctx *ctx, uint32_t *sum_dev, uint16_t *hist_dev, void *stream);
+
+/* Restores the accumulators from buffers laid out as in pca_get_accumulators, with the
+ * sample and tally counts that go with them (as pca_stats reports them).  Errors:
+ * PCA_EINVAL for NULL buffers, a histogram where the run has none, negative counts, or
+ * counts whose totals could overflow the accumulators (count * (levels-1) >= 2^32,
+ * tallies * chains > 65535). */
+int pca_set_accumulators(pca_ctx *ctx, const uint32_t *sum_dev, const uint16_t *hist_dev, int64_t count,
+                         int64_t tallies, void *stream);
+
 /* Waits for all work the context enqueued and reports any device error. */
 int pca_sync(pca_ctx *ctx);
 

@@ -105,6 +105,8 @@ def lib():
         L.orc_posterior_mean.argtypes = [pp, u32, ctypes.c_int64, f32]
         L.orc_marginal_map.argtypes = [pp, u16, u8]
         L.orc_constants.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, f32]
+        L.orc_draw.argtypes = [f32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]
+        L.orc_draw.restype = ctypes.c_int32
         for name in ("orc_init_state", "orc_run", "orc_update_sites", "orc_site_acc",
                      "orc_posterior_mean", "orc_marginal_map", "orc_constants"):
             getattr(L, name).restype = ctypes.c_int
@@ -244,6 +246,12 @@ def site_acc(p: Params, obs: np.ndarray, state: np.ndarray, chain: int, r: int, 
                             int(gibbs), _ptr(out, ctypes.c_float))
     _check(rc, "orc_site_acc")
     return out
+
+
+def draw(acc: np.ndarray, x: int, rword: int) -> int:
+    """The inverse-CDF draw from running sums [acc_-1, acc_0, ..., acc_{L-1}]."""
+    acc = np.ascontiguousarray(acc, dtype=np.float32)
+    return int(lib().orc_draw(_ptr(acc, ctypes.c_float), acc.size - 1, int(x), int(rword) & 0xFFFFFFFF))
 
 
 def site_probs(p: Params, obs, state, chain, r, c, t=0, gibbs=False) -> np.ndarray:

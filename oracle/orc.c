@@ -461,6 +461,14 @@ int orc_update_sites(const orc_params *p, const float *obs, const uint8_t *state
     return ORC_OK;
 }
 
+/* The draw of C5 from running sums acc[0..L] (acc[0] the stay weight), current level x
+ * and Philox word rword; for tests of the rule itself. */
+int32_t orc_draw(const float *acc, int32_t L, int32_t x, uint32_t rword)
+{
+    if (!acc || L < 1) return -1;
+    return draw_from_acc(acc, L, x, rword);
+}
+
 /* The running sums acc[0..L] of one site (see C4), for inspection by tests. */
 int orc_site_acc(const orc_params *p, const float *obs, const uint8_t *state, int32_t chain,
                  int32_t r, int32_t c, int64_t t, int32_t gibbs, float *acc)

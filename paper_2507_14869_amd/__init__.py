@@ -16,7 +16,7 @@ from ._lib import (PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_param
                    pca_batch_sweep, pca_batch_posterior_mean, pca_batch_marginal_map, pca_batch_get_state,
                    pca_batch_stats, pca_batch_sync, pca_batch_destroy, pca_server_create, pca_server_submit,
                    pca_server_step, pca_server_completed, pca_server_status, pca_server_result, pca_server_release,
-                   pca_server_stats, pca_server_destroy)
+                   pca_server_stats, pca_server_destroy, pca_get_accumulators, pca_set_accumulators)
 
 
 def _stream_handle(stream) -> int:
@@ -88,6 +88,31 @@ class Sampler:
     def stats(self):
         """(sweep index, samples in the mean, tally sweeps)."""
         return pca_stats(self.ctx)
+
+    def accumulators(self, stream=None):
+        """(sum, hist): the raw accumulators as int32 [H, W] and int16 [H, W, levels] CUDA
+        tensors holding the bits of the uint32 level sums and uint16 level tallies (hist is
+        None without a histogram).  With :meth:`state` and :meth:`stats` this checkpoints a
+        run; :meth:`set_accumulators` restores it."""
+        import torch
+        s = torch.empty((self.height, self.width), dtype=torch.int32, device=self.device)
+        h = (torch.empty((self.height, self.width, self.levels), dtype=torch.int16, device=self.device)
+             if self.params.tally_stride > 0 else None)
+        pca_get_accumulators(self.ctx, s.data_ptr(), h.data_ptr() if h is not None else 0, _stream_handle(stream))
+        return s, h
+
+    def set_accumulators(self, sum_, hist, count: int, tallies: int, stream=None) -> "Sampler":
+        import torch
+        if sum_.dtype != torch.int32 or tuple(sum_.shape) != (self.height, self.width) or not sum_.is_cuda:
+            raise ValueError("sum must be an int32 [H, W] CUDA tensor")
+        if hist is not None and (hist.dtype != torch.int16 or not hist.is_cuda
+                                 or tuple(hist.shape) != (self.height, self.width, self.levels)):
+            raise ValueError("hist must be an int16 [H, W, levels] CUDA tensor")
+        self._acc_bufs = (sum_.contiguous(), hist.contiguous() if hist is not None else None)
+        pca_set_accumulators(self.ctx, self._acc_bufs[0].data_ptr(),
+                             self._acc_bufs[1].data_ptr() if hist is not None else 0, count, tallies,
+                             _stream_handle(stream))
+        return self
 
     def sync(self):
         pca_sync(self.ctx)

@@ -296,6 +296,52 @@ int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream)
     return PCA_OK;
 }
 
+int pca_get_accumulators(pca_ctx *ctx, uint32_t *sum_dev, uint16_t *hist_dev, void *stream)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!sum_dev) return fail(PCA_EINVAL, "sum_dev is NULL");
+    if (hist_dev && !ctx->hist) return fail(PCA_EINVAL, "this run keeps no histogram");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    const size_t L = (size_t)ctx->p.levels;
+    hipError_t e = hipMemcpyAsync(sum_dev, ctx->sum, (size_t)ctx->N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    // the histogram row of a pixel is hist_words words of two uint16 counters (level 2w in
+    // the low half), i.e. 2*hist_words uint16 counters in level order on this little-endian
+    // device; the copy drops the unused counter of an odd level count
+    if (e == hipSuccess && hist_dev)
+        e = hipMemcpy2DAsync(hist_dev, L * sizeof(uint16_t), ctx->hist, (size_t)ctx->hist_words * sizeof(uint32_t),
+                             L * sizeof(uint16_t), (size_t)ctx->N, hipMemcpyDeviceToDevice, s);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_get_accumulators");
+}
+
+int pca_set_accumulators(pca_ctx *ctx, const uint32_t *sum_dev, const uint16_t *hist_dev, int64_t count,
+                         int64_t tallies, void *stream)
+{
+    g_err.clear();
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!sum_dev) return fail(PCA_EINVAL, "sum_dev is NULL");
+    if (hist_dev && !ctx->hist) return fail(PCA_EINVAL, "this run keeps no histogram");
+    if (!hist_dev && ctx->hist) return fail(PCA_EINVAL, "hist_dev is NULL but this run keeps a histogram");
+    if (count < 0 || tallies < 0) return fail(PCA_EINVAL, "counts must be >= 0");
+    if ((double)count * (double)(ctx->p.levels - 1) > 4294967295.0)
+        return fail(PCA_EINVAL, "count too large for the 32-bit level sum");
+    if (tallies * (int64_t)ctx->p.chains > 65535) return fail(PCA_EINVAL, "tallies too large for 16-bit counters");
+    hipStream_t s = (hipStream_t)stream;
+    ctx->last = s;
+    const size_t L = (size_t)ctx->p.levels;
+    hipError_t e = hipMemcpyAsync(ctx->sum, sum_dev, (size_t)ctx->N * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && hist_dev)
+        e = hipMemcpy2DAsync(ctx->hist, (size_t)ctx->hist_words * sizeof(uint32_t), hist_dev, L * sizeof(uint16_t),
+                             L * sizeof(uint16_t), (size_t)ctx->N, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "pca_set_accumulators");
+    ctx->count = count;
+    ctx->tallies = tallies;
+    return PCA_OK;
+}
+
 int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *tallies)
 {
     int rc = check_ctx(ctx);

@@ -299,6 +299,65 @@ def test_draw_frequencies_match_conditional(orc):
         assert chisq_pvalue(counts, probs) > 1e-4
 
 
+def _acc(weights, stay):
+    """FP32 running sums as the sampler forms them: the stay weight, then fma-free adds
+    of exactly representable weights (so the sums are exact)."""
+    acc = [np.float32(stay)]
+    for w in weights:
+        acc.append(np.float32(acc[-1] + np.float32(w)))
+    return np.array(acc, dtype=np.float32)
+
+
+def test_draw_rule_at_the_ends_of_the_uniform(orc):
+    """u = 0 takes the first positive weight in the order (stay, 0, 1, ..., L-1); the
+    largest u, 1 - 2^-24, takes the last positive one; zero weights are never drawn."""
+    w = [0.0, 0.0, 0.25, 0.5, 0.0, 0.125, 0.0]
+    acc = _acc(w, 0.0)
+    assert orc.draw(acc, 3, 0) == 2 and orc.draw(acc, 3, 255) == 2  # both give u = 0
+    assert orc.draw(acc, 3, 0xFFFFFFFF) == 5
+    acc = _acc(w, 0.0625)
+    assert orc.draw(acc, 6, 0) == 6             # positive stay weight: u = 0 stays, at a zero-weight level
+    assert orc.draw(acc, 6, 0xFFFFFFFF) == 5
+
+
+def test_draw_rule_is_monotone_and_exact_at_boundaries(orc):
+    """The drawn position in (stay, 0, ..., L-1) never decreases with u, and u exactly at
+    a cumulative boundary belongs to the next cell (strict inequality)."""
+    rng = np.random.default_rng(21)
+    for _ in range(20):
+        L = int(rng.integers(2, 12))
+        w = (rng.integers(0, 5, size=L) / 8.0).tolist()
+        stay = float(rng.integers(0, 3) / 8.0)
+        if sum(w) + stay == 0:
+            w[0] = 0.125
+        acc = _acc(w, stay)
+        x = int(rng.integers(0, L))
+        pos_of = lambda k, u_word: (-1 if k == x and float(acc[0]) > float(orc.uniform(u_word)) * float(acc[-1])  # noqa: E731
+                                    else k)
+        last = -2
+        for r in range(0, 1 << 24, 1 << 14):
+            word = r << 8
+            k = orc.draw(acc, x, word)
+            pos = pos_of(k, word)
+            assert pos >= last
+            last = pos
+        Z = float(acc[-1])
+        for j in range(1, L + 1):  # u with u*Z equal to the cumulative sum acc_{j-2}
+            c = float(acc[j - 1])
+            r = c / Z * (1 << 24)
+            if r == int(r) and 0 <= r < (1 << 24) and c > 0:
+                k = orc.draw(acc, x, int(r) << 8)
+                cum = acc[1:]
+                assert k == x or cum[k] > c
+
+
+def test_draw_keeps_the_state_when_every_weight_is_zero(orc):
+    acc = np.zeros(6, dtype=np.float32)
+    for x in range(5):
+        for word in (0, 0x12345678, 0xFFFFFFFF):
+            assert orc.draw(acc, x, word) == x
+
+
 def test_sweeps_compose_and_chains_are_independent_of_chain_count(orc):
     H, W, L = 6, 5, 16
     rng = np.random.default_rng(3)
