@@ -402,7 +402,9 @@ def main():
     ops_per_su = valu_ops_per_site_update(wl.levels, wl.chains, args.inertia)
     launch_ops = ops_per_su * N * wl.chains
     achieved = launch_ops / avg_launch_s / 1e12
-    traffic = measured_traffic(N * wl.chains) if args.inertia == 0 and wl.name == "c3" else None
+    # the committed counter summary is for the default c3 job (1000 sweeps, 250 of them burn-in)
+    default_job = args.inertia == 0 and wl.name == "c3" and args.sweeps is None and args.q is None
+    traffic = measured_traffic(N * wl.chains) if default_job else None
     hbm_alg = hbm_bytes_per_sweep(N, wl.chains, wl.tally_stride > 0)
     out = {
         "metric": "site-updates/s",

@@ -42,7 +42,8 @@ struct Request {
     int64_t id = 0;
     pca_params p{};
     std::vector<float> beta;
-    std::vector<float> obs;  // host copy until admission
+    std::vector<float> obs;      // host copy until the step that admits it has finished
+    std::vector<double> beta_d;  // beta in double, staged for the upload at admission
     int32_t sweeps = 0;
     size_t footprint = 0;
     pcak::ImageDesc d{};
@@ -144,11 +145,11 @@ int admit(pca_server *sv, Request *r, hipStream_t s)
         free_device(r);
         return fail(PCA_ENOMEM, "server: device allocation failed for request %lld", (long long)r->id);
     }
-    std::vector<double> beta(r->beta.begin(), r->beta.end());
+    r->beta_d.assign(r->beta.begin(), r->beta.end());
     d.beta = r->d_beta;
     e = hipMemcpyAsync(r->d_obs, r->obs.data(), N * sizeof(float), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && !beta.empty())
-        e = hipMemcpyAsync(r->d_beta, beta.data(), beta.size() * sizeof(double), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !r->beta_d.empty())
+        e = hipMemcpyAsync(r->d_beta, r->beta_d.data(), r->beta_d.size() * sizeof(double), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemsetAsync(d.sum, 0, N * sizeof(uint32_t), s);
     if (e == hipSuccess && d.hist) e = hipMemsetAsync(d.hist, 0, N * d.hist_words * sizeof(uint32_t), s);
     if (e == hipSuccess) {
@@ -166,15 +167,13 @@ int admit(pca_server *sv, Request *r, hipStream_t s)
         a.key1 = d.key1;
         e = pcak::launch_init(a, s);
     }
-    // the host copies must outlive the asynchronous uploads
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);
         free_device(r);
         return hip_fail(e, "server: admission");
     }
-    std::vector<float>().swap(r->obs);
-    (void)hipFree(r->d_obs);
-    r->d_obs = nullptr;
+    // the host copies and the device staging of the observation stay until the step that
+    // admitted the request has synchronised (release_staging)
     r->status = ACTIVE;
     sv->used += r->footprint;
     return PCA_OK;
@@ -207,6 +206,15 @@ int read_out(Request *r, hipStream_t s)
         if (e == hipSuccess) e = hipMemcpyAsync(r->mpm.data(), spare, (size_t)N, hipMemcpyDeviceToHost, s);
     }
     return e == hipSuccess ? PCA_OK : hip_fail(e, "server: read-out");
+}
+
+// After the admitting step's synchronisation: the uploads and the init kernel are done.
+void release_staging(Request *r)
+{
+    std::vector<float>().swap(r->obs);
+    std::vector<double>().swap(r->beta_d);
+    (void)hipFree(r->d_obs);
+    r->d_obs = nullptr;
 }
 
 int ensure_capacity(pca_server *sv, size_t blocks)
@@ -286,7 +294,10 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     hipStream_t s = (hipStream_t)stream;
     sv->last = s;
     if (n_completed) *n_completed = 0;
-    // 1. admission, first come first served, by device footprint and free slots
+    // 1. admission, first come first served, by device footprint and free slots (no
+    //    synchronisation here: the uploads and initialisations are stream-ordered before
+    //    the step's sweeps)
+    std::vector<Request *> admitted;
     while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active &&
            sv->used + sv->queue.front()->footprint <= sv->budget) {
         Request *r = sv->queue.front();
@@ -294,6 +305,7 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         if (rc) return rc;
         sv->queue.pop_front();
         sv->active.push_back(r);
+        admitted.push_back(r);
     }
     if (sv->active.empty()) return PCA_OK;
     // 2. sweeps per request this step: at least one each, then the step's GPU-time budget
@@ -426,6 +438,7 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     // uploads came from host vectors local to this call
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "server: step");
+    for (auto *r : admitted) release_staging(r);
     if (timed) {  // refine the cost model from the measured step
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess && units > 0.0 && ms > 0.0f)
