@@ -43,13 +43,27 @@ def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0) -> floa
     return levels * (6.0 + 15.0 / chains)
 
 
-def hbm_bytes_per_sweep(N: int, chains: int, tally: bool) -> float:
-    """State read and write, observation read, uint32 sum read-modify-write, and (tally
-    sweeps) one uint16 counter read-modify-write per chain."""
-    b = 2.0 * chains * N + 4.0 * N + 8.0 * N
+def hbm_bytes_per_sweep(N: int, chains: int, acc: bool, tally: bool) -> float:
+    """State read and write and observation read; on accumulating sweeps the uint32 sum
+    read-modify-write; on tally sweeps one uint16 counter read-modify-write per chain."""
+    b = 2.0 * chains * N + 4.0 * N
+    if acc:
+        b += 8.0 * N
     if tally:
         b += 4.0 * chains * N
     return b
+
+
+def hbm_bytes_per_launch(wl) -> float:
+    """Algorithmic bytes per sweep launch averaged over the job's sweeps (burn-in sweeps
+    accumulate nothing)."""
+    N = wl.height * wl.width
+    total = 0.0
+    for t in range(wl.sweeps):
+        acc = t >= wl.burn_in
+        tally = acc and wl.tally_stride > 0 and (t - wl.burn_in) % wl.tally_stride == 0
+        total += hbm_bytes_per_sweep(N, wl.chains, acc, tally)
+    return total / wl.sweeps
 
 
 def kernel_hash() -> str:
@@ -405,7 +419,7 @@ def main():
     # the committed counter summary is for the default c3 job (1000 sweeps, 250 of them burn-in)
     default_job = args.inertia == 0 and wl.name == "c3" and args.sweeps is None and args.q is None
     traffic = measured_traffic(N * wl.chains) if default_job else None
-    hbm_alg = hbm_bytes_per_sweep(N, wl.chains, wl.tally_stride > 0)
+    hbm_alg = hbm_bytes_per_launch(wl)
     out = {
         "metric": "site-updates/s",
         "value": value,
