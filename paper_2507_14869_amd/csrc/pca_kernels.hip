@@ -8,7 +8,7 @@ namespace {
 
 // One sweep of one lattice: thread gid = pixel * (Cp/G) + chain group, row-major pixels.
 template <int G, int NBR, int SUB, int NBLK, int SHARE>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs a)
+__global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel(SweepArgs a)
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
     const SweepConsts kc = sweep_prologue(a, NBR, ptab);

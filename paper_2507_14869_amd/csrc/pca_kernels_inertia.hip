@@ -8,7 +8,7 @@ namespace pcak {
 namespace {
 
 template <int G, int NBR, int SUB>
-__global__ __launch_bounds__(kBlock) void sweep_kernel_inertia(SweepArgs a)
+__global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel_inertia(SweepArgs a)
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
     const SweepConsts kc = sweep_prologue(a, NBR, ptab);

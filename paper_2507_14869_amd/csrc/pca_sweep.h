@@ -166,12 +166,22 @@ __device__ __forceinline__ float group_bcast(float v)
     }
 }
 
-template <int G, int NW>
+// GROUPED issues all G table reads before the first is consumed, so their LDS latencies
+// overlap (used in the 16-level blocks; the L <= 16 path measured faster without).
+template <int G, int NW, bool GROUPED = true>
 __device__ __forceinline__ void level_update(const char *pt, const NbrPack<NW> (&nb)[G], float (&acc)[G], float D,
                                              uint32_t kk)
 {
+    if constexpr (GROUPED) {
+        float P[G];
 #pragma unroll
-    for (int ch = 0; ch < G; ++ch) acc[ch] = __builtin_fmaf(D, prior_lookup<NW>(pt, nb[ch], kk), acc[ch]);
+        for (int ch = 0; ch < G; ++ch) P[ch] = prior_lookup<NW>(pt, nb[ch], kk);
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch) acc[ch] = __builtin_fmaf(D, P[ch], acc[ch]);
+    } else {
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch) acc[ch] = __builtin_fmaf(D, prior_lookup<NW>(pt, nb[ch], kk), acc[ch]);
+    }
 }
 
 // Levels J.. of a group of SHARE consecutive levels; only the first nlev exist.
@@ -387,7 +397,7 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
                         else if (j == 1) D = group_bcast<SHARE, (SHARE > 1 ? 1 : 0)>(Dm);
                         else if (j == 2) D = group_bcast<SHARE, (SHARE > 2 ? 2 : 0)>(Dm);
                         else D = group_bcast<SHARE, (SHARE > 3 ? 3 : 0)>(Dm);
-                        level_update<G, NW>(pt, nb, acc, D, kk);
+                        level_update<G, NW, false>(pt, nb, acc, D, kk);
                         kk += 0x01010101u;
 #pragma unroll
                         for (int ch = 0; ch < G; ++ch) part[k0 + j][ch] = acc[ch];
@@ -615,6 +625,15 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
 }
 
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+// Waves per SIMD the single-lattice sweep kernels are compiled for.  With 16-level blocks
+// (L > 16) the register allocator would otherwise settle at 127 VGPRs and 4 waves; at 5
+// waves (96 VGPRs) the LDS and DPP latencies of the level loop are better hidden although
+// about 19 values, mostly block partial sums, then go to scratch.  Measured on 2048x2048,
+// L = 256, 16 chains with the grouped table reads: 4 waves 3.06 ms per sweep, 5 waves 2.93,
+// 6 waves 2.90 with 2.5x the scratch write traffic, 7 and 8 waves slower.
+template <int SUB>
+constexpr int kMinWaves = SUB > 1 ? 5 : 1;
 
 }  // namespace
 }  // namespace pcak
