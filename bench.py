@@ -9,8 +9,15 @@ is resident in HBM before the timed region.  Prints one JSON line.
 
 Roofline: the sweep kernel is bound by vector ALU work; `roofline` reports its
 algorithmic VALU lane-operations per launch divided by its average launch time (HIP
-events on the launch stream) against the MI355X VALU issue rate.  `cpu_baseline` is
-the CPU reference timed on a bounded sample of the same workload on this host.
+events on the launch stream) against the MI355X VALU issue rate; `traffic` is the HBM
+bytes per launch from the committed rocprofv3 counter summary when it was taken on the
+current kernel source for this job.  `cpu_baseline` is the CPU reference timed on a
+bounded sample of the same workload on this host.
+
+Other workloads: --workload c1/c2 (smaller single images), c4 (a batch of 64 mixed
+lattices in one launch per sweep, against one launch per lattice), c5 (a Poisson stream
+of 250 mixed requests through the continuous-batching server, against one request at a
+time; latency percentiles); --inertia, --q and --neighbourhood vary the model on c1-c3.
 """
 from __future__ import annotations
 
@@ -32,15 +39,16 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_14869_amd", "csrc", f) for f in
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c3_traffic.txt")
 
 
-def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0) -> float:
+def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0, nbr: int = 4) -> float:
     """Algorithmic VALU lane-ops per site update.  Indicator inertia: per (chain, level)
-    three byte-SADs, the two-op table index and one fma; per (pixel, level) the 15-op data
-    factor shared by the chains of the pixel.  L1/L2 inertia: per (chain, level) those six
-    plus |k - x|^p and its conversion (3), the exponent (2 fma/mul, 1 subtraction) and
-    exp2s (9); per (pixel, level) e and e*e (2)."""
+    three byte-SADs per four neighbours, the two-op table index and one fma; per (pixel,
+    level) the 15-op data factor shared by the chains of the pixel.  L1/L2 inertia: per
+    (chain, level) those plus |k - x|^p and its conversion (3), the exponent (2 fma/mul, 1
+    subtraction) and exp2s (9); per (pixel, level) e and e*e (2)."""
+    sads = 3.0 * nbr / 4.0
     if inertia:
-        return levels * (21.0 + 2.0 / chains)
-    return levels * (6.0 + 15.0 / chains)
+        return levels * (sads + 18.0 + 2.0 / chains)
+    return levels * (sads + 3.0 + 15.0 / chains)
 
 
 def hbm_bytes_per_sweep(N: int, chains: int, acc: bool, tally: bool) -> float:
@@ -338,6 +346,8 @@ def main():
     ap.add_argument("--inertia", type=int, default=0, choices=[0, 1, 2],
                     help="c1-c3: inertia norm exponent (0 indicator, 1 L1, 2 L2)")
     ap.add_argument("--q", type=float, default=None, help="c1-c3: override the inertia weight q")
+    ap.add_argument("--neighbourhood", type=int, default=None, choices=[4, 8],
+                    help="c1-c3: override the neighbourhood (the paper's experiments use 8)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -367,6 +377,8 @@ def main():
     wl = synth.make_workload(args.workload, sweeps=args.sweeps)
     if args.q is not None:
         wl.q = args.q
+    if args.neighbourhood is not None:
+        wl.neighbourhood = args.neighbourhood
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     obs = torch.from_numpy(wl.obs).to(dev)
@@ -413,11 +425,12 @@ def main():
     su_total = wl.site_updates * args.steps
     value = su_total / elapsed
 
-    ops_per_su = valu_ops_per_site_update(wl.levels, wl.chains, args.inertia)
+    ops_per_su = valu_ops_per_site_update(wl.levels, wl.chains, args.inertia, wl.neighbourhood)
     launch_ops = ops_per_su * N * wl.chains
     achieved = launch_ops / avg_launch_s / 1e12
     # the committed counter summary is for the default c3 job (1000 sweeps, 250 of them burn-in)
-    default_job = args.inertia == 0 and wl.name == "c3" and args.sweeps is None and args.q is None
+    default_job = (args.inertia == 0 and wl.name == "c3" and args.sweeps is None and args.q is None
+                   and args.neighbourhood is None)
     traffic = measured_traffic(N * wl.chains) if default_job else None
     hbm_alg = hbm_bytes_per_launch(wl)
     out = {
@@ -436,7 +449,7 @@ def main():
         "config": {
             "workload": f"{wl.name}: {wl.height}x{wl.width} image, L={wl.levels}, {wl.chains} chains, "
                         f"{wl.sweeps} sweeps, truncated-linear prior T={wl.trunc} J={wl.J} q={wl.q}, "
-                        f"sigma={wl.sigma} levels, 4-neighbour, mean + marginal mode"
+                        f"sigma={wl.sigma} levels, {wl.neighbourhood}-neighbour, mean + marginal mode"
                         + ("" if args.inertia == 0 else f", L{args.inertia} inertia"),
             "inertia": args.inertia,
             "height": wl.height, "width": wl.width, "levels": wl.levels, "chains": wl.chains,
