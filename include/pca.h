@@ -86,7 +86,9 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
 /* Enqueues n >= 0 sweeps of the lazy PCA (Sec. 5.2): sweep t reads state t of every chain
  * and writes state t+1, drawing each site from its conditional given the previous state
  * only; then adds every chain's new levels to the mean accumulator if t >= burn_in and to
- * the histogram on tally sweeps.  n = 0 is a no-op.  Errors: PCA_EINVAL (n < 0),
+ * the histogram on tally sweeps.  n = 0 is a no-op.  A sweep of more than 2^31 threads
+ * (height*width*chains/4 for 3 or more chains) is enqueued as several kernel launches
+ * with the same results.  Errors: PCA_EINVAL (n < 0),
  * PCA_ESTATE (the uint32 sum or a uint16 histogram counter could overflow), PCA_EDEVICE. */
 int pca_sweep(pca_ctx *ctx, int32_t n, void *stream);
 

@@ -111,7 +111,7 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
             const int64_t threads = (int64_t)d.H * d.W * d.tpp;
             blocks = (int)((threads + pcak::kBlock - 1) / pcak::kBlock);
         }
-        if ((int64_t)base + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "batch too large for one launch");
+        if ((int64_t)base + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "batch grid exceeds 2^31 - 1 workgroups");
         block_img.insert(block_img.end(), (size_t)blocks, i);
         base += blocks;
     }

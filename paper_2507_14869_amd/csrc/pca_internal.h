@@ -11,6 +11,11 @@
 namespace pcak {
 
 constexpr int kBlock = 256;                 // threads per workgroup (4 wave64)
+// A dispatch counts its grid in 32-bit work-items, so a sweep with more threads than this
+// is split into launches of at most this many (a multiple of kBlock: every wave and lane
+// quad then holds the same threads as in a single launch).
+constexpr int64_t kMaxLaunchThreads = (int64_t)1 << 31;
+constexpr int kMaxLaunchBlocks = (int)(kMaxLaunchThreads / kBlock);
 constexpr int kMaxNeighbourStat = 8 * 255;  // largest S = sum_j min(|k-x_j|, T) over 8 neighbours
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
@@ -30,6 +35,7 @@ struct SweepArgs {
     uint32_t key0, key1;  // Philox key (seed split)
     uint32_t t;           // sweep index
     int inertia;          // inertia norm exponent: 0 (indicator, stay weight), 1 or 2
+    int64_t gid0;         // global index of the launch's first thread (split sweeps)
 };
 
 struct InitArgs {
@@ -69,19 +75,20 @@ struct BatchLaunch {
     const ImageDesc *imgs;
     const int *block_img;  // workgroup -> lattice
     uint32_t toff;         // sweep offset of this launch within the replay
+    int block0;            // first workgroup of this launch in the batch's grid (split grids)
 };
 
 constexpr int kTileW = 16;  // tiled traversal: tiles 16 pixels wide, kBlock / tpp pixels each
 
-// inr: the lattices use the L1/L2 inertia form (share is then ignored).
+// inr: the lattices use the L1/L2 inertia form (share is then ignored).  Grids of more
+// than kMaxLaunchBlocks workgroups are issued as several launches (BatchLaunch.block0).
 hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr, bool inr,
                               hipStream_t s);
 hipError_t launch_advance(ImageDesc *imgs, int n_imgs, uint32_t n, hipStream_t s);
 // The L1/L2 inertia kernels (pca_kernels_inertia.hip); the two launchers above hand over
 // to these when the sweep (or every lattice of the batch) has inertia 1 or 2.
 hipError_t launch_sweep_inertia(const SweepArgs &a, int G, int nbr, hipStream_t s);
-hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int total_blocks, int G, int tiled, int nbr,
-                                      hipStream_t s);
+hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int blocks, int G, int tiled, int nbr, hipStream_t s);
 
 // Shared by the single-lattice and batch entry points (pca_api.hip).
 int validate_params(const pca_params *p);     // PCA_OK or PCA_EINVAL with the error message set

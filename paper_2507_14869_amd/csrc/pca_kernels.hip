@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel(SweepArgs
     const SweepConsts kc = sweep_prologue(a, NBR, ptab);
     const int tpp = a.Cp / G;
     const int64_t N = (int64_t)a.H * a.W;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gid = a.gid0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (gid >= N * tpp) return;
     const int pix = (int)(gid / tpp);
     const int grp = (int)(gid - (int64_t)pix * tpp);
@@ -112,14 +112,20 @@ __global__ __launch_bounds__(kBlock) void mpm_kernel(const uint32_t *hist, uint8
 }
 
 template <int G, int NBR, int SHARE>
-hipError_t launch_sweep_gs(const SweepArgs &a, hipStream_t s)
+hipError_t launch_sweep_gs(const SweepArgs &a0, hipStream_t s)
 {
-    const int64_t threads = (int64_t)a.H * a.W * (a.Cp / G);
-    if (a.L <= 16)
-        hipLaunchKernelGGL((sweep_kernel<G, NBR, 1, 16, SHARE>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel<G, NBR, 16, 16, SHARE>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    const int64_t threads = (int64_t)a0.H * a0.W * (a0.Cp / G);
+    SweepArgs a = a0;
+    for (a.gid0 = 0; a.gid0 < threads; a.gid0 += kMaxLaunchThreads) {
+        const unsigned grid = grid_for(std::min(threads - a.gid0, kMaxLaunchThreads));
+        if (a.L <= 16)
+            hipLaunchKernelGGL((sweep_kernel<G, NBR, 1, 16, SHARE>), dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((sweep_kernel<G, NBR, 16, 16, SHARE>), dim3(grid), dim3(kBlock), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Threads per pixel = Cp / G; the data factor is shared by groups of 4 or 2 of them when

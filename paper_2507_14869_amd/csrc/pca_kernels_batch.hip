@@ -31,12 +31,9 @@ hipError_t launch_batch_gs(const BatchLaunch &b, int blocks, int tiled, int nbr,
     return tiled ? launch_batch_gst<G, SHARE, 1>(b, blocks, nbr, s) : launch_batch_gst<G, SHARE, 0>(b, blocks, nbr, s);
 }
 
-}  // namespace
-
-hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr, bool inr,
-                              hipStream_t s)
+hipError_t launch_batch_part(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr,
+                             hipStream_t s)
 {
-    if (inr) return launch_batch_sweep_inertia(b, total_blocks, G, tiled, nbr, s);
     if (G == 4) {
         if (share == 4) return launch_batch_gs<4, 4>(b, total_blocks, tiled, nbr, s);
         if (share == 2) return launch_batch_gs<4, 2>(b, total_blocks, tiled, nbr, s);
@@ -49,6 +46,22 @@ hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int
     if (share == 4) return launch_batch_gs<1, 4>(b, total_blocks, tiled, nbr, s);
     if (share == 2) return launch_batch_gs<1, 2>(b, total_blocks, tiled, nbr, s);
     return launch_batch_gs<1, 1>(b, total_blocks, tiled, nbr, s);
+}
+
+}  // namespace
+
+hipError_t launch_batch_sweep(const BatchLaunch &b0, int total_blocks, int G, int share, int tiled, int nbr, bool inr,
+                              hipStream_t s)
+{
+    BatchLaunch b = b0;
+    for (int64_t first = 0; first < total_blocks; first += kMaxLaunchBlocks) {
+        b.block0 = (int)first;
+        const int blocks = (int)std::min<int64_t>(total_blocks - first, kMaxLaunchBlocks);
+        const hipError_t e = inr ? launch_batch_sweep_inertia(b, blocks, G, tiled, nbr, s)
+                                 : launch_batch_part(b, blocks, G, share, tiled, nbr, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_advance(ImageDesc *imgs, int n_imgs, uint32_t n, hipStream_t s)

@@ -14,7 +14,7 @@ __global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel_inertia(S
     const SweepConsts kc = sweep_prologue(a, NBR, ptab);
     const int tpp = a.Cp / G;
     const int64_t N = (int64_t)a.H * a.W;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t gid = a.gid0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (gid >= N * tpp) return;
     const int pix = (int)(gid / tpp);
     const int grp = (int)(gid - (int64_t)pix * tpp);
@@ -23,14 +23,20 @@ __global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel_inertia(S
 }
 
 template <int G, int NBR>
-hipError_t launch_g(const SweepArgs &a, hipStream_t s)
+hipError_t launch_g(const SweepArgs &a0, hipStream_t s)
 {
-    const int64_t threads = (int64_t)a.H * a.W * (a.Cp / G);
-    if (a.L <= 16)
-        hipLaunchKernelGGL((sweep_kernel_inertia<G, NBR, 1>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((sweep_kernel_inertia<G, NBR, 16>), dim3(grid_for(threads)), dim3(kBlock), 0, s, a);
-    return hipGetLastError();
+    const int64_t threads = (int64_t)a0.H * a0.W * (a0.Cp / G);
+    SweepArgs a = a0;
+    for (a.gid0 = 0; a.gid0 < threads; a.gid0 += kMaxLaunchThreads) {
+        const unsigned grid = grid_for(std::min(threads - a.gid0, kMaxLaunchThreads));
+        if (a.L <= 16)
+            hipLaunchKernelGGL((sweep_kernel_inertia<G, NBR, 1>), dim3(grid), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((sweep_kernel_inertia<G, NBR, 16>), dim3(grid), dim3(kBlock), 0, s, a);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 template <int G, int TILED>
@@ -64,12 +70,11 @@ hipError_t launch_sweep_inertia(const SweepArgs &a, int G, int nbr, hipStream_t 
     return launch_g<1, 8>(a, s);
 }
 
-hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int total_blocks, int G, int tiled, int nbr,
-                                      hipStream_t s)
+hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int blocks, int G, int tiled, int nbr, hipStream_t s)
 {
-    if (G == 4) return launch_batch_g<4>(b, total_blocks, tiled, nbr, s);
-    if (G == 2) return launch_batch_g<2>(b, total_blocks, tiled, nbr, s);
-    return launch_batch_g<1>(b, total_blocks, tiled, nbr, s);
+    if (G == 4) return launch_batch_g<4>(b, blocks, tiled, nbr, s);
+    if (G == 2) return launch_batch_g<2>(b, blocks, tiled, nbr, s);
+    return launch_batch_g<1>(b, blocks, tiled, nbr, s);
 }
 
 }  // namespace pcak

@@ -392,6 +392,7 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         }
         d.t = (uint32_t)r->t;
         d.t_end = (uint32_t)(r->t + k[r]);
+        if ((int64_t)block_img.size() + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "server: step grid too large");
         block_img.insert(block_img.end(), (size_t)blocks, (int)desc.size());
         blocks_upto.push_back((int)block_img.size());
         desc.push_back(d);

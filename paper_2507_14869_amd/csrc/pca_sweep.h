@@ -569,7 +569,8 @@ template <int G, int SHARE, int TILED, int NBR, bool INR = false>
 __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
-    const int img = b.block_img[blockIdx.x];
+    const int blk = (int)blockIdx.x + b.block0;
+    const int img = b.block_img[blk];
     const ImageDesc &d = b.imgs[img];
     const uint32_t t = d.t + b.toff;
     if (t >= d.t_end) return;  // this lattice has finished (uniform over the workgroup)
@@ -597,10 +598,11 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
     a.key1 = d.key1;
     a.t = t;
     a.inertia = d.inertia;
+    a.gid0 = 0;
     const SweepConsts kc = sweep_prologue(a, NBR, ptab);
 
     const int tpp = d.tpp;
-    const int local = (int)blockIdx.x - d.block_base;
+    const int local = blk - d.block_base;
     int pix, r, c, grp;
     if constexpr (TILED == 0) {
         const int64_t gid = (int64_t)local * kBlock + threadIdx.x;

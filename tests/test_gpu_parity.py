@@ -151,6 +151,40 @@ def test_inertia_norm_stepwise_parity(orc, case):
     assert np.array_equal(gpu2.marginal_map().cpu().numpy(), ref2.marginal_map())
 
 
+@pytest.mark.parametrize("case", [
+    # (H, W, L, chains, nbr, prior, T, J, q, sigma, observation, inertia exponent)
+    (24, 20, 256, 4, 8, 1, 255, 0.02, 1.0, 20.0, "image", 0),    # largest prior table: 8*255 + 1 entries
+    (19, 23, 256, 16, 4, 1, 32, 0.05, 1.0, 5.0, "outside", 0),   # observations far outside [vmin, vmax]
+    (21, 17, 33, 3, 4, 1, 4, 0.3, 1.0, 0.01, "image", 0),        # sigma 0.01 levels: the data decides
+    (18, 22, 16, 8, 8, 1, 4, 0.4, 1.5, 1e5, "image", 0),         # flat data term
+    (20, 20, 16, 2, 4, 1, 4, 20.0, 0.5, 2.0, "image", 0),        # prior factors underflow to zero
+    (17, 19, 2, 5, 4, 0, 1, 0.8, 69.0, 0.3, "image", 0),         # q at its bound, beta q log2(e) < 100
+    (22, 18, 200, 4, 8, 0, 1, 3.0, 0.5, 10.0, "outside", 0),     # strong Potts coupling, many levels
+    (21, 19, 256, 4, 8, 1, 255, 0.02, 0.05, 20.0, "outside", 1),  # L1 inertia, largest table, far data
+    (17, 16, 64, 2, 4, 1, 8, 0.3, 0.5, 0.01, "image", 2),        # L2 inertia with a sharp data term
+])
+def test_extreme_parameters(orc, case):
+    """Parameters at the edges of the accepted range, where weights underflow, the stay
+    weight is near its largest value or the observation lies far outside the level range:
+    the same trajectories, means and modes as the CPU reference."""
+    H, W, L, C, nbr, prior, T, J, q, sigma, observation, p = case
+    if observation == "outside":
+        obs = np.random.default_rng(H * W).uniform(-300.0, 600.0, size=(H, W)).astype(np.float32)
+    else:
+        obs = _obs(H, W, L, seed=H * 100 + W, sigma=min(sigma, 0.2 * L))
+    beta = [1.0] if q * 1.4427 * 1.5 > 100.0 else [1.0, 1.25, 1.5]
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=nbr, prior=prior, trunc=T, J=J, q=q,
+              sigma=sigma, vmin=0.0, vmax=float(L - 1), beta=beta, seed=6161 + H, burn_in=1, tally_stride=1,
+              inertia=p, init_mode=1)
+    bad, total, ref, gpu = stepwise(orc, obs, 4, **kw)
+    assert bad <= FLIP_BUDGET * total, f"{bad} of {total} site updates differ"
+    ref2 = oracle_run(orc, obs, **kw).sweep(10)
+    gpu2 = gpu_sampler(obs, **kw).sweep(10)
+    assert np.array_equal(gpu2.state().cpu().numpy(), ref2.state)
+    assert np.array_equal(gpu2.posterior_mean().cpu().numpy(), ref2.posterior_mean())
+    assert np.array_equal(gpu2.marginal_map().cpu().numpy(), ref2.marginal_map())
+
+
 @pytest.mark.parametrize("C", [12, 32, 100, 1024])
 def test_many_chains_per_pixel(orc, C):
     """Chain counts whose lanes per pixel (chains / 4) are 3, 8, 25 and 256: pixels whose
@@ -167,6 +201,45 @@ def test_many_chains_per_pixel(orc, C):
     assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
     assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
     assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+
+
+def test_sweeps_larger_than_one_launch(orc):
+    """16384 x 16400 pixels with 64 chains: 4.3e9 threads per sweep, more than one dispatch
+    can count, so each sweep is issued as three launches (the last one ragged).  Chains 0-3
+    must equal an unsplit run with 4 chains everywhere, that run must equal the CPU
+    reference at sampled sites around the launch boundaries, and the mean accumulator must
+    hold the per-pixel sum of the new state over all 64 chains."""
+    torch = torch_cuda()
+    H, W = 16384, 16400
+    rng = np.random.default_rng(8)
+    yy = np.arange(H, dtype=np.int32)[:, None]
+    xx = np.arange(W, dtype=np.int32)[None, :]
+    obs = np.where(((yy // 512) + (xx // 640)) % 2 == 0, np.float32(1.0), np.float32(-1.0))
+    obs += np.float32(0.6) * rng.standard_normal((H, W), dtype=np.float32)
+    kw = dict(height=H, width=W, levels=2, neighbourhood=4, prior=0, trunc=1, J=0.8, q=2.0, sigma=0.6, vmin=-1.0,
+              vmax=1.0, seed=1616, burn_in=0, tally_stride=0)
+    big = gpu_sampler(obs, chains=64, **kw).sweep(1)
+    small = gpu_sampler(obs, chains=4, **kw).sweep(1)
+    assert big.stats() == (1, 64, 0)
+    sb = big.state()
+    ss = small.state()
+    assert torch.equal(sb[:4], ss)
+    acc, _ = big.accumulators()
+    assert torch.equal(sb.sum(dim=0, dtype=torch.int32), acc)
+    del sb, acc
+    big.close()
+    N = H * W
+    split = [(1 << 31) // 16, (1 << 32) // 16]  # first pixels of the second and third launch
+    pix = np.concatenate([[0, W - 1, N - W, N - 1], [p + d for p in split for d in (-W, -1, 0, 1, W)],
+                          rng.integers(0, N, size=3000)]).astype(np.int64)
+    chains = rng.integers(0, 4, size=pix.shape[0]).astype(np.int32)
+    p4 = orc.Params(chains=4, **kw)
+    want = orc.update_sites(p4, obs, orc.init_state(p4, obs), 0, chains, pix)
+    got = ss.view(4, -1)[torch.from_numpy(chains).long().cuda(), torch.from_numpy(pix).cuda()].cpu().numpy()
+    assert np.array_equal(got, want)
+    del ss
+    small.close()
+    torch.cuda.empty_cache()
 
 
 def test_sweep_splitting_is_invisible(orc):
