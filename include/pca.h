@@ -146,8 +146,7 @@ const char *pca_last_error(void);
  * Batches.  Many independent lattices - each with its own size, level count, chains,
  * parameters, beta schedule and seed, all with the same neighbourhood - advanced
  * together: every sweep of the batch is ONE kernel launch covering all lattices, and
- * the launches of a pca_batch_sweep call are captured once into a HIP graph and
- * replayed.  Each lattice's results are bit-identical to running it alone with
+ * the launches are replayed from captured HIP graphs.  Each lattice's results are bit-identical to running it alone with
  * pca_init/pca_sweep (the draws are keyed by its own seed, chain, sweep and pixel).
  * All lattices share one sweep index.  Conventions as above; `i` selects a lattice.
  * ------------------------------------------------------------------------------------ */
@@ -162,9 +161,12 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
 
 /* Launch-configuration autotuner: times every valid configuration (chains per thread
  * 1/2/4, lanes sharing a pixel's data factor 1/2/4, row-major or 16-pixel-wide tiled
- * traversal) over trial_sweeps sweeps of this batch, keeps the fastest, then restores the
+ * traversal) over trial_sweeps (1..64) burn-in sweeps and trial_sweeps accumulating
+ * sweeps of this batch (each lattice from sweep 0 and from its burn-in length), in two
+ * rounds, keeps the configuration with the smallest time of a round, then restores the
  * initial states (sweep index 0, accumulators cleared).  Synchronous.  *best_ms (may be
- * NULL) receives the winner's time per sweep.  The configuration never changes results. */
+ * NULL) receives the winner's mean time per trial sweep.  The configuration never changes
+ * results. */
 int pca_batch_autotune(pca_batch *b, int32_t trial_sweeps, void *stream, float *best_ms);
 
 /* The launch configuration in use, or set one explicitly (PCA_EINVAL if not valid for the
@@ -172,9 +174,10 @@ int pca_batch_autotune(pca_batch *b, int32_t trial_sweeps, void *stream, float *
 int pca_batch_config(const pca_batch *b, int32_t *chains_per_thread, int32_t *share, int32_t *tiled);
 int pca_batch_set_config(pca_batch *b, int32_t chains_per_thread, int32_t share, int32_t tiled, void *stream);
 
-/* Enqueues n >= 0 sweeps of every lattice (as pca_sweep).  The first call with a given n
- * captures and instantiates a graph (a few ms); later calls replay it.  Errors: PCA_EINVAL,
- * PCA_ESTATE (accumulator overflow), PCA_EDEVICE. */
+/* Enqueues n >= 0 sweeps of every lattice (as pca_sweep).  The sweeps are replayed from
+ * cached HIP graphs of at most 64 launches each (n = 64q + r replays the 64-sweep graph q
+ * times and an r-sweep graph once); a graph is captured and instantiated on first use (a
+ * few ms).  Errors: PCA_EINVAL, PCA_ESTATE (accumulator overflow), PCA_EDEVICE. */
 int pca_batch_sweep(pca_batch *b, int32_t n, void *stream);
 
 /* Per-lattice readouts and statistics, as pca_posterior_mean, pca_marginal_map,

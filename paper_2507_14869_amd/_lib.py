@@ -17,8 +17,8 @@ PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE = 0, -1, -2, -3, -4
 PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR = 0, 1
 
 EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "pca_get_state", "pca_set_state",
-            "pca_stats", "pca_get_accumulators", "pca_set_accumulators", "pca_sync", "pca_destroy", "pca_batch_init", "pca_batch_autotune", "pca_batch_config",
-            "pca_batch_set_config", "pca_batch_sweep", "pca_batch_posterior_mean", "pca_batch_marginal_map",
+            "pca_stats", "pca_get_accumulators", "pca_set_accumulators", "pca_sync", "pca_destroy",
+            "pca_batch_init", "pca_batch_autotune", "pca_batch_config", "pca_batch_set_config", "pca_batch_sweep", "pca_batch_posterior_mean", "pca_batch_marginal_map",
             "pca_batch_get_state", "pca_batch_stats", "pca_batch_sync", "pca_batch_destroy", "pca_server_create",
             "pca_server_submit", "pca_server_step", "pca_server_completed", "pca_server_status", "pca_server_result",
             "pca_server_release", "pca_server_stats", "pca_server_destroy", "pca_last_error")

@@ -15,7 +15,6 @@
 #include "pca_internal.h"
 
 struct pca_ctx {
-    int device = 0;
     pca_params p{};
     std::vector<float> beta;
     int G = 1, Cp = 1, T = 1;
@@ -131,7 +130,6 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
     ctx->p = *params;
     if (params->beta_len > 0) ctx->beta.assign(params->beta, params->beta + params->beta_len);
     ctx->p.beta = nullptr;
-    (void)hipGetDevice(&ctx->device);
     ctx->G = pcak::chain_group(params->chains);
     ctx->Cp = (params->chains + ctx->G - 1) / ctx->G * ctx->G;
     ctx->T = params->prior == PCA_PRIOR_POTTS ? 1 : (params->trunc < params->levels - 1 ? params->trunc
@@ -139,10 +137,6 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
     ctx->N = (int64_t)params->height * params->width;
     ctx->hist_words = (params->levels + 1) / 2;
     ctx->last = s;
-    if ((ctx->N * (ctx->Cp / ctx->G) + pcak::kBlock - 1) / pcak::kBlock > 0x7FFFFFFF) {
-        delete ctx;
-        return fail(PCA_EINVAL, "lattice times chains too large for one launch");
-    }
 
     const size_t N = (size_t)ctx->N;
     hipError_t e = hipMalloc(&ctx->gp, N * sizeof(float));

@@ -17,6 +17,11 @@
 
 namespace {
 
+// Sweeps per cached graph: a longer pca_batch_sweep call replays the 64-sweep graph (the
+// sweep index lives in device memory) and one graph for the remainder, so graph sizes and
+// the number of cached graphs stay bounded whatever n the caller passes.
+constexpr int32_t kGraphSweeps = 64;
+
 struct LaunchConfig {
     int G = 1, share = 1, tiled = 0;
     bool operator<(const LaunchConfig &o) const
@@ -42,7 +47,6 @@ double level_scale(const pca_params &p) { return (double)(p.levels - 1) / ((doub
 }  // namespace
 
 struct pca_batch {
-    int device = 0;
     int n = 0;
     int nbr = 4;
     bool inr = false;  // L1/L2 inertia kernels
@@ -224,6 +228,20 @@ int enqueue_eager(pca_batch *b, int32_t n, hipStream_t s)
     return e == hipSuccess ? PCA_OK : hip_fail(e, "batch sweep");
 }
 
+// Device sweep index of every lattice for an autotuner trial: 0 (burn-in sweeps) or its
+// burn-in length (accumulating sweeps, with tallies).  The run is re-initialised afterwards.
+int set_trial_index(pca_batch *b, bool accumulating, hipStream_t s)
+{
+    for (int i = 0; i < b->n; ++i) {
+        b->desc[i].t = accumulating ? (uint32_t)b->p[i].burn_in : 0u;
+        b->desc[i].t_end = 0xFFFFFFFFu;
+    }
+    hipError_t e = hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size() * sizeof(pcak::ImageDesc),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "batch autotune: trial set-up");
+}
+
 hipGraphExec_t graph_for(pca_batch *b, int32_t n, int *rc)
 {
     auto it = b->graphs.find(n);
@@ -276,7 +294,6 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
     b->nbr = params[0].neighbourhood;
     b->inr = params[0].inertia != 0;
     b->last = s;
-    (void)hipGetDevice(&b->device);
     b->p.assign(params, params + n);
     b->count.assign(n, 0);
     b->tallies.assign(n, 0);
@@ -353,43 +370,48 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
 int pca_batch_autotune(pca_batch *b, int32_t trial_sweeps, void *stream, float *best_ms)
 {
     if (!b) return fail(PCA_EINVAL, "batch is NULL");
-    if (trial_sweeps < 1) return fail(PCA_EINVAL, "trial_sweeps must be >= 1");
+    if (trial_sweeps < 1 || trial_sweeps > 64) return fail(PCA_EINVAL, "trial_sweeps must be in [1, 64]");
     hipStream_t s = (hipStream_t)stream;
     b->last = s;
-    for (int i = 0; i < b->n; ++i)
-        if (b->p[i].init_mode != 0 && b->p[i].init_mode != 1) return fail(PCA_EINVAL, "bad init mode");
-    hipEvent_t e0, e1;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
         return fail(PCA_EDEVICE, "batch autotune: event creation failed");
-    LaunchConfig best = b->cfg;
-    float best_t = 1e30f;
+    }
+    const std::vector<LaunchConfig> cands = candidates(b);
+    std::vector<float> score(cands.size(), 1e30f);
     int rc = PCA_OK;
-    for (const auto &c : candidates(b)) {
-        rc = apply_config(b, c, s);
-        if (rc) break;
-        rc = enqueue_eager(b, 1, s);  // warm-up
-        if (rc) break;
-        (void)hipEventRecord(e0, s);
-        rc = enqueue_eager(b, trial_sweeps, s);
-        (void)hipEventRecord(e1, s);
-        if (rc) break;
-        if (hipEventSynchronize(e1) != hipSuccess) {
-            rc = fail(PCA_EDEVICE, "batch autotune: timing failed");
-            break;
-        }
-        float ms = 0.0f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        if (ms < best_t) {
-            best_t = ms;
-            best = c;
+    // two rounds over the candidates, each timing burn-in and accumulating sweeps; a
+    // candidate keeps its best round
+    for (int round = 0; round < 2 && rc == PCA_OK; ++round) {
+        for (size_t ci = 0; ci < cands.size() && rc == PCA_OK; ++ci) {
+            rc = apply_config(b, cands[ci], s);
+            float total = 0.0f;
+            for (int phase = 0; phase < 2 && rc == PCA_OK; ++phase) {
+                rc = set_trial_index(b, phase == 1, s);
+                if (rc == PCA_OK) rc = enqueue_eager(b, 1, s);  // warm-up
+                if (rc) break;
+                (void)hipEventRecord(e0, s);
+                rc = enqueue_eager(b, trial_sweeps, s);
+                (void)hipEventRecord(e1, s);
+                if (rc) break;
+                float ms = 0.0f;
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    rc = fail(PCA_EDEVICE, "batch autotune: timing failed");
+                total += ms;
+            }
+            if (rc == PCA_OK) score[ci] = std::min(score[ci], total);
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (rc == PCA_OK) rc = apply_config(b, best, s);
+    size_t best = 0;
+    for (size_t ci = 1; ci < cands.size(); ++ci)
+        if (score[ci] < score[best]) best = ci;
+    if (rc == PCA_OK) rc = apply_config(b, cands[best], s);
     if (rc == PCA_OK) rc = reset_run(b, nullptr, s);
     if (rc == PCA_OK && hipStreamSynchronize(s) != hipSuccess) rc = fail(PCA_EDEVICE, "batch autotune: reset failed");
-    if (best_ms) *best_ms = best_t / (float)trial_sweeps;
+    if (best_ms) *best_ms = score[best] / (float)(2 * trial_sweeps);
     return rc;
 }
 
@@ -422,10 +444,17 @@ int pca_batch_sweep(pca_batch *b, int32_t n, void *stream)
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     b->last = s;
-    hipGraphExec_t ex = graph_for(b, n, &rc);
-    if (!ex) return rc;
-    hipError_t e = hipGraphLaunch(ex, s);
-    if (e != hipSuccess) return hip_fail(e, "batch sweep: graph launch");
+    const int32_t full = n / kGraphSweeps, rest = n % kGraphSweeps;
+    hipGraphExec_t ex_full = full > 0 ? graph_for(b, kGraphSweeps, &rc) : nullptr;
+    if (full > 0 && !ex_full) return rc;
+    hipGraphExec_t ex_rest = rest > 0 ? graph_for(b, rest, &rc) : nullptr;
+    if (rest > 0 && !ex_rest) return rc;
+    for (int32_t i = 0; i <= full; ++i) {
+        hipGraphExec_t ex = i < full ? ex_full : ex_rest;
+        if (!ex) break;
+        hipError_t e = hipGraphLaunch(ex, s);
+        if (e != hipSuccess) return hip_fail(e, "batch sweep: graph launch");
+    }
     b->t += n;
     for (int i = 0; i < b->n; ++i) {
         b->count[i] += add_count[i];

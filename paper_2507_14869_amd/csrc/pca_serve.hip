@@ -73,7 +73,6 @@ size_t footprint_of(const pca_params &p)
 }  // namespace
 
 struct pca_server {
-    int device = 0;
     size_t budget = 0, used = 0;
     int max_active = 0, sweeps_per_step = 0;
     double step_ms = 20.0;        // GPU time a step aims at
@@ -217,6 +216,18 @@ void release_staging(Request *r)
     r->d_obs = nullptr;
 }
 
+// The two timing events of a step, destroyed on every return path.
+struct StepEvents {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    bool ok = false;
+    StepEvents() { ok = hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess; }
+    ~StepEvents()
+    {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+    }
+};
+
 int ensure_capacity(pca_server *sv, size_t blocks)
 {
     if (blocks <= sv->block_cap) return PCA_OK;
@@ -244,7 +255,6 @@ int pca_server_create(uint64_t hbm_budget_bytes, int32_t max_active, int32_t swe
         return fail(PCA_EINVAL, "need a positive budget, 1..4096 active requests, sweeps_per_step >= 1 and "
                                 "step_ms > 0");
     pca_server *sv = new pca_server();
-    (void)hipGetDevice(&sv->device);
     sv->budget = (size_t)hbm_budget_bytes;
     sv->max_active = max_active;
     sv->sweeps_per_step = sweeps_per_step;
@@ -308,9 +318,8 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         admitted.push_back(r);
     }
     if (sv->active.empty()) return PCA_OK;
-    // 2. sweeps per request this step: at least one each, then the step's GPU-time budget
-    //    goes to the requests with the least remaining work, so small requests finish in
-    //    one step instead of being paced by the largest ones
+    // 2. sweeps per request this step: at least one each, then the rest of the step's
+    //    GPU-time budget (below).
     // one launch runs one kernel: the requests sharing the oldest one's neighbourhood and
     // inertia form advance now, the others in a later step
     const int nbr = sv->active.front()->p.neighbourhood;
@@ -405,16 +414,15 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     if (e == hipSuccess)
         e = hipMemcpyAsync(sv->d_block_img, block_img.data(), block_img.size() * sizeof(int), hipMemcpyHostToDevice, s);
     const int K = (int)k[launched.front()];
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    const bool timed = hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
-    if (timed) (void)hipEventRecord(ev0, s);
+    StepEvents ev;
+    if (ev.ok) (void)hipEventRecord(ev.e0, s);
     size_t j = launched.size();
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         while (j > 0 && k[launched[j - 1]] <= i) --j;  // requests still advancing at launch i
         pcak::BatchLaunch bl{sv->d_desc, sv->d_block_img, (uint32_t)i};
         e = pcak::launch_batch_sweep(bl, blocks_upto[j - 1], G, share, tiled, nbr, inr, s);
     }
-    if (timed) (void)hipEventRecord(ev1, s);
+    if (ev.ok) (void)hipEventRecord(ev.e1, s);
     if (e != hipSuccess) return hip_fail(e, "server: sweep launch");
     sv->steps += 1;
     sv->sweeps_launched += K;
@@ -440,12 +448,10 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "server: step");
     for (auto *r : admitted) release_staging(r);
-    if (timed) {  // refine the cost model from the measured step
+    if (ev.ok) {  // refine the cost model from the measured step
         float ms = 0.0f;
-        if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess && units > 0.0 && ms > 0.0f)
+        if (hipEventElapsedTime(&ms, ev.e0, ev.e1) == hipSuccess && units > 0.0 && ms > 0.0f)
             sv->ns_per_unit = 0.7 * sv->ns_per_unit + 0.3 * (ms * 1e6 / units);
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
     }
     for (auto *r : finished) {
         free_device(r);

@@ -67,6 +67,28 @@ def test_batch_matches_lattices_run_alone(config):
     b.close()
 
 
+def test_long_calls_replay_bounded_graphs():
+    """150 sweeps in one call replay the 64-sweep graph twice and a 22-sweep graph once;
+    70 + 80 sweeps replay 64 + 6 and 64 + 16.  Both equal every lattice run alone."""
+    problems = [_problem(*spec[:4], seed=spec[4]) for spec in MIXED[:4]]
+    one = _batch(problems)
+    one.sweep(150)
+    two = _batch(problems)
+    two.sweep(70)
+    two.sweep(80)
+    for i, (obs, kw) in enumerate(problems):
+        ref = _alone(obs, kw, 150)
+        want = ref.state().cpu().numpy()
+        assert np.array_equal(one.state(i).cpu().numpy(), want), i
+        assert np.array_equal(two.state(i).cpu().numpy(), want), i
+        assert np.array_equal(one.posterior_mean(i).cpu().numpy(), ref.posterior_mean().cpu().numpy())
+        assert np.array_equal(two.marginal_map(i).cpu().numpy(), ref.marginal_map().cpu().numpy())
+        assert one.stats(i) == ref.stats() == two.stats(i)
+        ref.close()
+    one.close()
+    two.close()
+
+
 def test_batch_with_mixed_chain_counts():
     problems = [_problem(*spec[:4], seed=spec[4]) for spec in MIXED_CHAINS]
     b = _batch(problems)
