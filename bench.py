@@ -224,10 +224,12 @@ def bench_serve(args):
     """Poisson arrivals at 50 requests/s (sides log-uniform in [64, 4096], L in {2, 16, 256},
     sigma ~ U[0.1, 0.3] L, 2 chains, 300 sweeps) through the continuous-batching server, and
     through a one-request-at-a-time baseline on the same trace.  Latency is measured from
-    each request's scheduled arrival to the end of the step that finished it."""
+    each request's scheduled arrival to the end of the step that finished it.  With
+    --shed-backlog-s the server refuses submissions while its predicted wait exceeds the
+    limit; latency, throughput and quality are then over the requests it served."""
     import numpy as np
     import torch
-    from paper_2507_14869_amd import Sampler, Server
+    from paper_2507_14869_amd import PCA_EBUSY, PcaError, Sampler, Server
     from workloads import metrics, synth
 
     sweeps = args.sweeps or 300
@@ -242,18 +244,24 @@ def bench_serve(args):
 
     def run_server():
         sv = Server(160 << 30, max_active=512, sweeps_per_step=sweeps, step_ms=args.step_ms)
+        sv.set_shedding(args.shed_backlog_s)
         done_at, rid_of = {}, {}
         i = 0
         t0 = time.perf_counter()
         busy = 0.0
-        while len(done_at) < len(reqs):
+        while len(done_at) < len(rid_of) or i < len(reqs):
             now = time.perf_counter() - t0
             while i < len(reqs) and arrivals[i] <= now:
-                rid_of[sv.submit(reqs[i].obs, sweeps, **kws[i])] = i
+                try:
+                    rid_of[sv.submit(reqs[i].obs, sweeps, **kws[i])] = i
+                except PcaError as err:  # refused by the shedding limit
+                    if err.code != PCA_EBUSY:
+                        raise
                 i += 1
             q, a, _, _, _ = sv.stats()
             if q == 0 and a == 0:
-                time.sleep(max(0.0, min(arrivals[i] - now, 0.05)))
+                if i < len(reqs):
+                    time.sleep(max(0.0, min(arrivals[i] - now, 0.05)))
                 continue
             ts = time.perf_counter()
             sv.step()
@@ -267,8 +275,9 @@ def bench_serve(args):
             results[k] = sv.result(rid)[0]
         steps = sv.stats()[3]
         sv.close()
-        lat = np.array([done_at[k] - arrivals[k] for k in range(len(reqs))])
-        return lat, makespan, busy, steps, results
+        served = sorted(results)
+        lat = np.array([done_at[k] - arrivals[k] for k in served])
+        return lat, makespan, busy, steps, results, served
 
     def run_sequential():
         done_at = {}
@@ -293,17 +302,19 @@ def bench_serve(args):
     warm.close()
     torch.cuda.synchronize()
 
-    lat, makespan, busy, steps, results = run_server()
+    lat, makespan, busy, steps, results, served = run_server()
+    su_served = sum(reqs[k].height * reqs[k].width * reqs[k].chains for k in served) * sweeps
     lat_seq, makespan_seq = run_sequential()
     psnr_gain = []
-    for k, w in enumerate(reqs):
+    for k in served:
+        w = reqs[k]
         truth = metrics.luminance_levels(w.truth, w.levels)
         noisy = metrics.luminance_values(np.clip(w.obs, w.vmin, w.vmax), w.vmin, w.vmax)
         est = metrics.luminance_values(results[k], w.vmin, w.vmax)
         psnr_gain.append(metrics.psnr(truth, est) - metrics.psnr(truth, noisy))
     out = {
         "metric": "site-updates/s",
-        "value": su_total / makespan,
+        "value": su_served / makespan,
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": 1,
@@ -319,9 +330,11 @@ def bench_serve(args):
                         f"L in {{2, 16, 256}}, 2 chains, {sweeps} sweeps, continuous batching, {args.step_ms} ms steps",
             "requests": len(reqs), "site_updates": su_total,
         },
+        "shedding": {"max_backlog_s": args.shed_backlog_s, "served": len(served), "shed": len(reqs) - len(served),
+                     "shed_fraction": 1.0 - len(served) / len(reqs)},
         "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                       "mean": float(lat.mean()), "max": float(lat.max())},
-        "requests_per_s": len(reqs) / makespan,
+        "requests_per_s": len(served) / makespan,
         "gpu_busy_fraction": busy / makespan,
         "server_steps": steps,
         "mean_psnr_gain_db": float(np.mean(psnr_gain)),
@@ -342,6 +355,8 @@ def main():
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=250, help="c5: number of requests in the trace")
     ap.add_argument("--step-ms", type=float, default=20.0, help="c5: GPU time per server step")
+    ap.add_argument("--shed-backlog-s", type=float, default=0.0,
+                    help="c5: refuse submissions while the predicted wait exceeds this (0: never)")
     ap.add_argument("--sweeps", type=int, default=None, help="override the workload's sweep count")
     ap.add_argument("--inertia", type=int, default=0, choices=[0, 1, 2],
                     help="c1-c3: inertia norm exponent (0 indicator, 1 L1, 2 L2)")

@@ -45,7 +45,8 @@ enum {
     PCA_EINVAL = -1,  /* invalid argument or parameter */
     PCA_ENOMEM = -2,  /* device allocation failed */
     PCA_EDEVICE = -3, /* HIP runtime or kernel error */
-    PCA_ESTATE = -4   /* operation not valid in the context's current state */
+    PCA_ESTATE = -4,  /* operation not valid in the context's current state */
+    PCA_EBUSY = -5    /* request refused by the server's load-shedding limit */
 };
 
 enum {
@@ -216,9 +217,20 @@ int pca_server_create(uint64_t hbm_budget_bytes, int32_t max_active, int32_t swe
 /* Queues a request: parameters as for pca_init, the observation as a HOST float32
  * [height][width] array (copied), and the number of sweeps to run.  *request_id receives
  * a positive id.  Errors: PCA_EINVAL (invalid parameters, a footprint above the whole
- * budget, or accumulators that could overflow). */
+ * budget, or accumulators that could overflow), PCA_EBUSY (refused by the shedding limit,
+ * see pca_server_set_shedding). */
 int pca_server_submit(pca_server *sv, const pca_params *params, const float *obs_host, int32_t sweeps,
                       int64_t *request_id);
+
+/* Load shedding.  With max_backlog_s > 0, pca_server_submit refuses a request with
+ * PCA_EBUSY when the remaining work of the requests already accepted (admitted or queued),
+ * converted to seconds by the server's cost model (refined from every measured step), is
+ * above max_backlog_s; an idle server accepts any request that fits the budget.  0 (the
+ * default) disables shedding.  Errors: PCA_EINVAL (NULL server, negative limit). */
+int pca_server_set_shedding(pca_server *sv, double max_backlog_s);
+
+/* Number of submissions refused by the shedding limit so far. */
+int pca_server_shed_count(const pca_server *sv, int64_t *shed);
 
 /* One scheduling step on `stream` (synchronous: returns when the step's work is done).
  * *n_completed (may be NULL) receives the number of requests finished in this step. */

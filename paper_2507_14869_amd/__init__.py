@@ -10,13 +10,14 @@ from __future__ import annotations
 from typing import Optional, Sequence
 
 from . import _lib
-from ._lib import (PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_params, pca_destroy, pca_get_state,  # noqa
-                   pca_init, pca_last_error, pca_marginal_map, pca_posterior_mean, pca_set_state, pca_stats,
+from ._lib import (PCA_EBUSY, PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_params, pca_destroy,  # noqa
+                   pca_get_state, pca_init, pca_last_error, pca_marginal_map, pca_posterior_mean, pca_set_state, pca_stats,
                    pca_sweep, pca_sync, pca_batch_init, pca_batch_autotune, pca_batch_config, pca_batch_set_config,
                    pca_batch_sweep, pca_batch_posterior_mean, pca_batch_marginal_map, pca_batch_get_state,
                    pca_batch_stats, pca_batch_sync, pca_batch_destroy, pca_server_create, pca_server_submit,
                    pca_server_step, pca_server_completed, pca_server_status, pca_server_result, pca_server_release,
-                   pca_server_stats, pca_server_destroy, pca_get_accumulators, pca_set_accumulators)
+                   pca_server_stats, pca_server_set_shedding, pca_server_shed_count, pca_server_destroy,
+                   pca_get_accumulators, pca_set_accumulators)
 
 
 def _stream_handle(stream) -> int:
@@ -216,8 +217,10 @@ class Server:
 
     ``submit(obs, sweeps, **params)`` takes a host float32 [H, W] numpy array; ``step()``
     admits what fits the device-memory budget and advances every admitted request (at least
-    one sweep each, the rest of a ``step_ms`` GPU-time budget to the requests with the least
-    remaining work); ``result(id)`` returns (mean, mode, states) as numpy arrays.
+    one sweep each, the rest of a ``step_ms`` GPU-time budget half to the requests with the
+    least remaining work, half to the oldest); ``result(id)`` returns (mean, mode, states)
+    as numpy arrays.  ``set_shedding(s)`` makes ``submit`` raise :class:`PcaError` with
+    code ``PCA_EBUSY`` while the predicted wait of the accepted work exceeds ``s`` seconds.
     """
 
     def __init__(self, hbm_budget_bytes: int, max_active: int = 256, sweeps_per_step: int = 300,
@@ -237,6 +240,14 @@ class Server:
 
     def step(self, stream=None) -> int:
         return pca_server_step(self.sv, _stream_handle(stream))
+
+    def set_shedding(self, max_backlog_s: float):
+        pca_server_set_shedding(self.sv, max_backlog_s)
+
+    @property
+    def shed(self) -> int:
+        """Submissions refused by the shedding limit so far."""
+        return pca_server_shed_count(self.sv)
 
     def completed(self):
         return pca_server_completed(self.sv)

@@ -13,7 +13,7 @@ from typing import Optional, Sequence
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpca.so")
 
-PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE = 0, -1, -2, -3, -4
+PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE, PCA_EBUSY = 0, -1, -2, -3, -4, -5
 PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR = 0, 1
 
 EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "pca_get_state", "pca_set_state",
@@ -21,7 +21,8 @@ EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "
             "pca_batch_init", "pca_batch_autotune", "pca_batch_config", "pca_batch_set_config", "pca_batch_sweep", "pca_batch_posterior_mean", "pca_batch_marginal_map",
             "pca_batch_get_state", "pca_batch_stats", "pca_batch_sync", "pca_batch_destroy", "pca_server_create",
             "pca_server_submit", "pca_server_step", "pca_server_completed", "pca_server_status", "pca_server_result",
-            "pca_server_release", "pca_server_stats", "pca_server_destroy", "pca_last_error")
+            "pca_server_release", "pca_server_stats", "pca_server_set_shedding", "pca_server_shed_count",
+            "pca_server_destroy", "pca_last_error")
 
 
 class PcaError(RuntimeError):
@@ -91,6 +92,8 @@ def load():
         lib.pca_server_result.argtypes = [vp, ctypes.c_int64, vp, vp, vp]
         lib.pca_server_release.argtypes = [vp, ctypes.c_int64]
         lib.pca_server_stats.argtypes = [vp, i32p, i32p, u64p, i64p, i64p]
+        lib.pca_server_set_shedding.argtypes = [vp, ctypes.c_double]
+        lib.pca_server_shed_count.argtypes = [vp, i64p]
         lib.pca_server_destroy.argtypes = [vp]
         lib.pca_last_error.argtypes = []
         lib.pca_last_error.restype = ctypes.c_char_p
@@ -259,6 +262,16 @@ def pca_server_submit(sv: int, params: pca_params, obs_host_ptr: int, sweeps: in
     _check(load().pca_server_submit(ctypes.c_void_p(sv), ctypes.byref(params), ctypes.c_void_p(obs_host_ptr),
                                     int(sweeps), ctypes.byref(rid)), "pca_server_submit")
     return rid.value
+
+
+def pca_server_set_shedding(sv: int, max_backlog_s: float):
+    _check(load().pca_server_set_shedding(ctypes.c_void_p(sv), float(max_backlog_s)), "pca_server_set_shedding")
+
+
+def pca_server_shed_count(sv: int) -> int:
+    n = ctypes.c_int64()
+    _check(load().pca_server_shed_count(ctypes.c_void_p(sv), ctypes.byref(n)), "pca_server_shed_count")
+    return n.value
 
 
 def pca_server_step(sv: int, stream: int = 0) -> int:

@@ -86,6 +86,8 @@ struct pca_server {
     int *d_block_img = nullptr;
     size_t block_cap = 0;
     int64_t steps = 0, sweeps_launched = 0;
+    double max_backlog_s = 0.0;  // shedding limit on the predicted wait; 0 = none
+    int64_t shed = 0;            // submissions refused by it
     hipStream_t last = nullptr;
 };
 
@@ -216,6 +218,15 @@ void release_staging(Request *r)
     r->d_obs = nullptr;
 }
 
+// Remaining work of the accepted requests (admitted and queued), in cost-model units.
+double backlog_units(const pca_server *sv)
+{
+    double u = 0.0;
+    for (const auto *r : sv->active) u += (double)(r->sweeps - r->t) * units_per_sweep(r->p);
+    for (const auto *r : sv->queue) u += (double)(r->sweeps - r->t) * units_per_sweep(r->p);
+    return u;
+}
+
 // The two timing events of a step, destroyed on every return path.
 struct StepEvents {
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -280,21 +291,41 @@ int pca_server_submit(pca_server *sv, const pca_params *params, const float *obs
         return fail(PCA_EINVAL, "the level sum of this request could overflow 32 bits");
     if (p.tally_stride > 0 && ((acc + p.tally_stride - 1) / p.tally_stride) * (int64_t)p.chains > 65535)
         return fail(PCA_EINVAL, "a histogram counter of this request could overflow 16 bits");
+    if (footprint_of(p) > sv->budget) return fail(PCA_EINVAL, "request needs more device memory than the whole budget");
+    if (sv->max_backlog_s > 0.0) {  // load shedding: the wait predicted by the cost model
+        const double wait_s = backlog_units(sv) * sv->ns_per_unit * 1e-9;
+        if (wait_s > sv->max_backlog_s) {
+            sv->shed += 1;
+            return fail(PCA_EBUSY, "server: predicted wait %.3f s exceeds the shedding limit %.3f s", wait_s,
+                        sv->max_backlog_s);
+        }
+    }
     Request *r = new Request();
     r->p = p;
     if (p.beta_len > 0) r->beta.assign(p.beta, p.beta + p.beta_len);
     r->p.beta = nullptr;
     r->sweeps = sweeps;
     r->footprint = footprint_of(p);
-    if (r->footprint > sv->budget) {
-        delete r;
-        return fail(PCA_EINVAL, "request needs more device memory than the whole budget");
-    }
     r->obs.assign(obs_host, obs_host + (size_t)p.height * p.width);
     r->id = sv->next_id++;
     sv->queue.push_back(r);
     sv->all[r->id] = r;
     *request_id = r->id;
+    return PCA_OK;
+}
+
+int pca_server_set_shedding(pca_server *sv, double max_backlog_s)
+{
+    if (!sv) return fail(PCA_EINVAL, "server is NULL");
+    if (!(max_backlog_s >= 0.0)) return fail(PCA_EINVAL, "max_backlog_s must be >= 0");
+    sv->max_backlog_s = max_backlog_s;
+    return PCA_OK;
+}
+
+int pca_server_shed_count(const pca_server *sv, int64_t *shed)
+{
+    if (!sv || !shed) return fail(PCA_EINVAL, "NULL argument");
+    *shed = sv->shed;
     return PCA_OK;
 }
 

@@ -123,6 +123,35 @@ def test_server_rejects_bad_requests():
     sv.close()
 
 
+def test_shedding_refuses_requests_while_the_backlog_is_long():
+    """With a shedding limit, a submission is refused (PCA_EBUSY) while accepted work is
+    pending and accepted again once the server has drained; the accepted request's result
+    equals the request run alone.  A limit of 0 accepts everything."""
+    from paper_2507_14869_amd import PCA_EBUSY, PcaError
+    sv = _server(budget=1 << 32, k=8, step_ms=0.5)
+    obs, kw = _problem(48, 40, 16, 2, 21)
+    sv.set_shedding(1e-9)  # any pending work is too much
+    first = sv.submit(obs, 24, **kw)  # an idle server accepts
+    with pytest.raises(PcaError) as err:
+        sv.submit(obs, 24, **kw)
+    assert err.value.code == PCA_EBUSY
+    assert sv.shed == 1
+    while sv.status(first)[0] != 2:
+        sv.step()
+    again = sv.submit(obs, 24, **kw)  # drained: accepted again
+    mean, mpm, state = sv.result(first)
+    want = _alone(obs, kw, 24)
+    assert np.array_equal(mean, want[0]) and np.array_equal(mpm, want[1]) and np.array_equal(state, want[2])
+    sv.set_shedding(0.0)
+    extra = [sv.submit(obs, 24, **kw) for _ in range(3)]
+    assert sv.shed == 1
+    with pytest.raises(PcaError):
+        sv.set_shedding(-1.0)
+    while any(sv.status(r)[0] != 2 for r in [again] + extra):
+        sv.step()
+    sv.close()
+
+
 def test_requests_with_different_kernels_share_the_server():
     """Requests needing different kernels (4 or 8 neighbours, indicator or L2 inertia)
     are served in the same steps' rotation and each equals its run alone."""
