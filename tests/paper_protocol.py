@@ -141,7 +141,7 @@ def main():
     ap.add_argument("--gs-runs", type=int, default=3, help="independent Gibbs runs per image")
     ap.add_argument("--threads", type=int, default=min(16, os.cpu_count() or 1))
     ap.add_argument("--images", type=int, default=len(IMAGES), help="use the first n images")
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "paper_protocol.json"))
+    ap.add_argument("--out", default="paper_protocol.json", help="where to write the results (JSON)")
     args = ap.parse_args()
     images = IMAGES[:args.images]
     pool = ThreadPoolExecutor(max_workers=args.threads)  # the CPU reference releases the GIL

@@ -67,7 +67,7 @@ class Workload:
 PARAM_KEYS = ("height", "width", "levels", "chains", "neighbourhood", "prior", "trunc", "J", "q", "sigma",
               "vmin", "vmax", "beta", "seed", "burn_in", "tally_stride")
 
-CONFIGS = {
+WORKLOAD_RECIPES = {
     "c1": dict(height=64, width=64, levels=2, chains=1, sweeps=200, prior=POTTS, trunc=1, J=0.8, q=2.0,
                sigma=0.6, vmin=-1.0, vmax=1.0, shapes=5, gradient=False, burn_in=50, tally_stride=1),
     "c2": dict(height=512, width=512, levels=16, chains=8, sweeps=1000, prior=TRUNC_LINEAR, trunc=4, J=0.4,
@@ -138,7 +138,7 @@ def noisy_observation(truth: np.ndarray, levels: int, vmin: float, vmax: float, 
 def make_workload(name: str, *, height: Optional[int] = None, width: Optional[int] = None,
                   chains: Optional[int] = None, sweeps: Optional[int] = None) -> Workload:
     """Named workload c1/c2/c3 with its truth and observation (optionally resized)."""
-    cfg = dict(CONFIGS[name])
+    cfg = dict(WORKLOAD_RECIPES[name])
     idx = CONFIG_INDEX[name]
     if height is not None:
         cfg["height"] = height
