@@ -78,6 +78,10 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
+// WIDE: each 32x32-bit product as one 64-bit multiply (v_mad_u64_u32, cheaper than a low
+// and a high multiply; used where registers are not scarce: the kernels for L <= 16 spill
+// nothing, while in the 16-level-block kernels the register pairs cost extra spills).
+template <bool WIDE = false>
 __device__ __forceinline__ U4 philox(U4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
@@ -86,8 +90,20 @@ __device__ __forceinline__ U4 philox(U4 c, uint32_t k0, uint32_t k1)
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+        uint32_t lo0, hi0, lo1, hi1;
+        if constexpr (WIDE) {
+            const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+            const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+            lo0 = (uint32_t)p0;
+            hi0 = (uint32_t)(p0 >> 32);
+            lo1 = (uint32_t)p1;
+            hi1 = (uint32_t)(p1 >> 32);
+        } else {
+            lo0 = 0xD2511F53u * c.x;
+            hi0 = __umulhi(0xD2511F53u, c.x);
+            lo1 = 0xCD9E8D57u * c.z;
+            hi1 = __umulhi(0xCD9E8D57u, c.z);
+        }
         c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
     }
     return c;
@@ -446,7 +462,7 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
 
     // Inverse-CDF draw for each chain.
     const int chain0 = cofs;
-    const U4 rnd = philox(U4{(uint32_t)pix, a.t, (uint32_t)(chain0 >> 2), 0u}, a.key0, a.key1);
+    const U4 rnd = philox<SUB == 1>(U4{(uint32_t)pix, a.t, (uint32_t)(chain0 >> 2), 0u}, a.key0, a.key1);
     uint32_t packed = 0u;
     uint32_t lsum = 0u;
     int knew[G];
