@@ -90,7 +90,8 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
  * the histogram on tally sweeps.  n = 0 is a no-op.  A sweep of more than 2^31 threads
  * (height*width*chains/4 for 3 or more chains) is enqueued as several kernel launches
  * with the same results.  Errors: PCA_EINVAL (n < 0),
- * PCA_ESTATE (the uint32 sum or a uint16 histogram counter could overflow), PCA_EDEVICE. */
+ * PCA_ESTATE (the uint32 sum or a uint16 histogram counter could overflow, or the sweep
+ * index, a 32-bit counter word of the random stream, would pass 2^32 - 1), PCA_EDEVICE. */
 int pca_sweep(pca_ctx *ctx, int32_t n, void *stream);
 
 /* Writes the posterior-mean estimate (Sec. 2, conditional mean; Monte Carlo average over

@@ -183,14 +183,12 @@ int pca_sweep(pca_ctx *ctx, int32_t n, void *stream)
     if (n < 0) return fail(PCA_EINVAL, "n must be >= 0");
     if (n == 0) return PCA_OK;
     const pca_params &p = ctx->p;
+    // the sweep index is a 32-bit Philox counter word: beyond it the draws would repeat
+    if (ctx->t + n > 0xFFFFFFFFll) return fail(PCA_ESTATE, "the sweep index would pass 2^32 - 1");
     // Overflow guards: the uint32 level sum and the uint16 histogram counters.
-    int64_t add_count = 0, add_tallies = 0;
-    for (int64_t t = ctx->t; t < ctx->t + n; ++t) {
-        if (t >= p.burn_in) {
-            add_count += p.chains;
-            if (p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0) add_tallies += 1;
-        }
-    }
+    int64_t add_sweeps = 0, add_tallies = 0;
+    pcak::accumulating_sweeps(ctx->t, n, p.burn_in, p.tally_stride, &add_sweeps, &add_tallies);
+    const int64_t add_count = add_sweeps * p.chains;
     if ((double)(ctx->count + add_count) * (double)(p.levels - 1) > 4294967295.0)
         return fail(PCA_ESTATE, "the level sum could overflow 32 bits");
     if ((ctx->tallies + add_tallies) * (int64_t)p.chains > 65535)

@@ -201,12 +201,9 @@ int check_guards(const pca_batch *b, int32_t n, std::vector<int64_t> *add_count,
     add_tally->assign(b->n, 0);
     for (int i = 0; i < b->n; ++i) {
         const pca_params &p = b->p[i];
-        for (int64_t t = b->t; t < b->t + n; ++t) {
-            if (t >= p.burn_in) {
-                (*add_count)[i] += p.chains;
-                if (p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0) (*add_tally)[i] += 1;
-            }
-        }
+        int64_t sweeps = 0;
+        pcak::accumulating_sweeps(b->t, n, p.burn_in, p.tally_stride, &sweeps, &(*add_tally)[i]);
+        (*add_count)[i] = sweeps * p.chains;
         if ((double)(b->count[i] + (*add_count)[i]) * (double)(p.levels - 1) > 4294967295.0)
             return fail(PCA_ESTATE, "lattice %d: the level sum could overflow 32 bits", i);
         if ((b->tallies[i] + (*add_tally)[i]) * (int64_t)p.chains > 65535)

@@ -48,6 +48,22 @@ struct InitArgs {
     uint32_t key0, key1;
 };
 
+// Sweeps t0 .. t0+n-1 of a run with the given burn-in and tally stride: how many of them
+// accumulate into the mean (t >= burn_in) and how many also tally the histogram
+// ((t - burn_in) % stride == 0; none if stride <= 0).
+inline void accumulating_sweeps(int64_t t0, int64_t n, int64_t burn_in, int64_t stride, int64_t *acc,
+                                int64_t *tallies)
+{
+    const int64_t a = t0 > burn_in ? t0 : burn_in, b = t0 + n;  // accumulating sweeps: [a, b)
+    *acc = b > a ? b - a : 0;
+    *tallies = 0;
+    if (stride > 0 && b > a) {
+        // multiples of stride in [0, x) for x >= 0
+        auto upto = [stride](int64_t x) { return x <= 0 ? (int64_t)0 : (x - 1) / stride + 1; };
+        *tallies = upto(b - burn_in) - upto(a - burn_in);
+    }
+}
+
 // Chains handled by one thread: 4 (one Philox call feeds four chains) unless fewer exist.
 inline int chain_group(int chains) { return chains >= 3 ? 4 : chains; }
 // Chain slots in the interleaved state: chains rounded up to a multiple of 4 (1 or 2 stay).

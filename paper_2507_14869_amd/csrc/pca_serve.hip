@@ -461,12 +461,10 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     std::vector<Request *> finished;
     for (auto *r : launched) {
         const int64_t adv = k[r];
-        for (int64_t t = r->t; t < r->t + adv; ++t) {
-            if (t >= r->p.burn_in) {
-                r->count += r->p.chains;
-                if (r->p.tally_stride > 0 && (t - r->p.burn_in) % r->p.tally_stride == 0) r->tallies += 1;
-            }
-        }
+        int64_t sweeps = 0, tallies = 0;
+        pcak::accumulating_sweeps(r->t, adv, r->p.burn_in, r->p.tally_stride, &sweeps, &tallies);
+        r->count += sweeps * r->p.chains;
+        r->tallies += tallies;
         r->t += adv;
         if (r->t >= r->sweeps) {
             rc = read_out(r, s);

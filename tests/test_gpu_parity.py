@@ -282,6 +282,23 @@ def test_streams_and_errors():
     g.close()
 
 
+def test_sweep_index_stops_at_32_bits():
+    """The sweep index is a 32-bit counter word of the random stream: sweeps may run up to
+    it, and a call that would pass 2^32 - 1 is refused without side effects."""
+    from paper_2507_14869_amd import PcaError
+    wl = synth.make_workload("c2", height=16, width=16)
+    g = gpu_sampler(wl.obs, **wl.params(burn_in=0))
+    g.set_state(g.state(), (1 << 32) - 3)
+    g.sweep(2)
+    assert g.stats()[0] == (1 << 32) - 1
+    before = g.state().cpu().numpy()
+    with pytest.raises(PcaError):
+        g.sweep(1)
+    assert g.stats()[0] == (1 << 32) - 1
+    assert np.array_equal(g.state().cpu().numpy(), before)
+    g.close()
+
+
 def test_full_size_c3_sampled_sites(orc):
     """2048x2048, L = 256, 16 chains in the benchmark's launch configuration: one sweep from
     the oracle's initial state and one from an oracle-made random state at sweep 777,
