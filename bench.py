@@ -101,26 +101,49 @@ def measured_traffic(per_launch_units: float):
         return None
 
 
-def cpu_baseline(wl, seconds: float, inertia: int = 0):
-    """The oracle on sampled site updates of sweep 0 of the same workload, single thread."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(wl, seconds: float, inertia: int = 0, threads: int = 1):
+    """The oracle on sampled site updates of sweep 0 of the same workload, in `threads`
+    host threads (the oracle's C code runs outside the interpreter lock), each drawing its
+    own random (chain, pixel) sample for `seconds`."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
     p = oracle.Params(**wl.params(inertia=inertia))
     x0 = oracle.init_state(p, wl.obs)
-    rng = np.random.default_rng(7)
     N = wl.height * wl.width
-    done = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        n = 4096
-        ch = rng.integers(0, wl.chains, n).astype(np.int32)
-        px = rng.integers(0, N, n).astype(np.int64)
-        oracle.update_sites(p, wl.obs, x0, 0, ch, px)
-        done += n
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+
+    def worker(seed):
+        rng = np.random.default_rng(seed)
+        done = 0
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            n = 4096
+            ch = rng.integers(0, wl.chains, n).astype(np.int32)
+            px = rng.integers(0, N, n).astype(np.int64)
+            oracle.update_sites(p, wl.obs, x0, 0, ch, px)
+            done += n
+        return done, time.perf_counter() - t0
+
+    with ThreadPoolExecutor(max_workers=threads) as pool:
+        res = list(pool.map(worker, [7 + i for i in range(threads)]))
+    done = sum(r[0] for r in res)
+    dt = max(r[1] for r in res)
+    how = "single-threaded" if threads == 1 else f"in {threads} threads"
+    return {"value": done / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{done} random (chain, pixel) site updates of sweep 0 of the same {wl.height}x{wl.width} "
-                      f"L={wl.levels} workload, {dt:.1f} s single-threaded"}
+                      f"L={wl.levels} workload, {dt:.1f} s {how}",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def copy_probe(mib: int, reps: int = 4):
@@ -489,8 +512,26 @@ def main():
         },
         "level_evaluations_per_s": value * wl.levels,
     }
+    # one more job with the observation starting in host memory and the mean and mode
+    # ending there: the end-to-end time a caller holding host arrays sees (not `value`)
+    obs_host = wl.obs.copy()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = Sampler(torch.from_numpy(obs_host).to(dev), levels=levels, **kw)
+    s.sweep(wl.sweeps)
+    s.posterior_mean().cpu()
+    if wl.tally_stride > 0:
+        s.marginal_map().cpu()
+    torch.cuda.synchronize()
+    e2e = time.perf_counter() - t0
+    s.close()
+    out["end_to_end"] = {"ms_per_job": e2e * 1e3, "site_updates_per_s": wl.site_updates / e2e,
+                         "includes": "observation upload from host memory, the job, mean and mode download"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.inertia)
+        threads = min(16, len(os.sched_getaffinity(0)))
+        if threads > 1:
+            out["cpu_baseline_all_cores"] = cpu_baseline(wl, args.cpu_seconds, args.inertia, threads)
     print(json.dumps(out), flush=True)
 
 
