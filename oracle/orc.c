@@ -68,6 +68,15 @@
  *      maximises the real-valued form: for p = 1, kc = min(max(x, g' - h), g' + h) with
  *      h = q2 / (2*a2); for p = 2, kc = (a2*g' + q2*x) / (a2 + q2).  Gibbs has no
  *      inertia at any p.
+ *
+ * What pins this code (the CPU tests): the per-site conditionals against closed forms and
+ * float64 evaluations, the whole samplers' laws against exactly enumerated transition
+ * matrices and closed-form stationary laws, exp2s against its error bound, Philox against
+ * an independent library implementation of the same published generator, the draw rule
+ * on constructed sums.  The bit-level choices of C1-C6 (rounding order, the Philox
+ * counter layout, the exact threshold comparison) are conventions the paper does not fix:
+ * parity unpinned by the paper beyond those laws and bounds; a frozen fixture guards them
+ * against unintended change.
  */
 #include <math.h>
 #include <stdint.h>
