@@ -391,8 +391,9 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         const double left = grant(by_work, budget / 2) + budget / 2;
         grant(by_age, left);
     }
-    // launch configuration valid for every request of the step
-    int G = 1, share = 1, tiled = 1;
+    // launch configuration valid for every request of the step; row-major traversal (on the
+    // serving trace it kept the GPU busy 2% less than 16-pixel-wide tiles)
+    int G = 1, share = 1;
     for (int g : {4, 2}) {
         bool ok = true;
         for (auto *r : cand) ok = ok && r->d.Cp % g == 0;
@@ -409,7 +410,6 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
             break;
         }
     }
-    for (auto *r : cand) tiled = tiled && (r->d.Cp / G) <= pcak::kBlock / pcak::kTileW;
     // lay the requests out by decreasing sweep count, so launch i covers a prefix of the grid
     std::vector<Request *> launched(cand);
     std::stable_sort(launched.begin(), launched.end(), [&](Request *a, Request *b) { return k[a] > k[b]; });
@@ -421,15 +421,8 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         pcak::ImageDesc d = r->d;
         d.tpp = d.Cp / G;
         d.block_base = (int)block_img.size();
-        int blocks;
-        if (tiled) {
-            const int th = pcak::kBlock / d.tpp / pcak::kTileW;
-            d.tiles_w = (d.W + pcak::kTileW - 1) / pcak::kTileW;
-            blocks = d.tiles_w * ((d.H + th - 1) / th);
-        } else {
-            d.tiles_w = 0;
-            blocks = (int)(((int64_t)d.H * d.W * d.tpp + pcak::kBlock - 1) / pcak::kBlock);
-        }
+        d.tiles_w = 0;
+        const int64_t blocks = ((int64_t)d.H * d.W * d.tpp + pcak::kBlock - 1) / pcak::kBlock;
         d.t = (uint32_t)r->t;
         d.t_end = (uint32_t)(r->t + k[r]);
         if ((int64_t)block_img.size() + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "server: step grid too large");
@@ -451,7 +444,7 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         while (j > 0 && k[launched[j - 1]] <= i) --j;  // requests still advancing at launch i
         pcak::BatchLaunch bl{sv->d_desc, sv->d_block_img, (uint32_t)i};
-        e = pcak::launch_batch_sweep(bl, blocks_upto[j - 1], G, share, tiled, nbr, inr, s);
+        e = pcak::launch_batch_sweep(bl, blocks_upto[j - 1], G, share, 0, nbr, inr, s);
     }
     if (ev.ok) (void)hipEventRecord(ev.e1, s);
     if (e != hipSuccess) return hip_fail(e, "server: sweep launch");
