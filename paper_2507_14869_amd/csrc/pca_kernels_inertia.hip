@@ -12,23 +12,20 @@ __global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel_inertia(S
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
     const SweepConsts kc = sweep_prologue(a, NBR, ptab);
-    const int tpp = a.Cp / G;
-    const int64_t N = (int64_t)a.H * a.W;
-    const int64_t gid = a.gid0 + (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (gid >= N * tpp) return;
-    const int pix = (int)(gid / tpp);
-    const int grp = (int)(gid - (int64_t)pix * tpp);
-    const int r = pix / a.W;
-    sweep_site<G, NBR, SUB, 16, 1, true>(a, ptab, kc, pix, r, pix - r * a.W, grp, 0);
+    int pix, r, c, grp;
+    if (!sweep_thread_site(a, a.Cp / G, pix, r, c, grp)) return;
+    sweep_site<G, NBR, SUB, 16, 1, true>(a, ptab, kc, pix, r, c, grp, 0);
 }
 
 template <int G, int NBR>
 hipError_t launch_g(const SweepArgs &a0, hipStream_t s)
 {
-    const int64_t threads = (int64_t)a0.H * a0.W * (a0.Cp / G);
+    const SweepLayout lay = sweep_layout(a0.H, a0.W, a0.Cp / G, false);
     SweepArgs a = a0;
-    for (a.gid0 = 0; a.gid0 < threads; a.gid0 += kMaxLaunchThreads) {
-        const unsigned grid = grid_for(std::min(threads - a.gid0, kMaxLaunchThreads));
+    a.patch = lay.patch;
+    a.tiles_w = lay.tiles_w;
+    for (a.blk0 = 0; a.blk0 < lay.blocks; a.blk0 += kMaxLaunchBlocks) {
+        const unsigned grid = (unsigned)std::min<int64_t>(lay.blocks - a.blk0, kMaxLaunchBlocks);
         if (a.L <= 16)
             hipLaunchKernelGGL((sweep_kernel_inertia<G, NBR, 1>), dim3(grid), dim3(kBlock), 0, s, a);
         else

@@ -614,7 +614,9 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
     a.key1 = d.key1;
     a.t = t;
     a.inertia = d.inertia;
-    a.gid0 = 0;
+    a.blk0 = 0;
+    a.patch = -1;
+    a.tiles_w = 0;
     const SweepConsts kc = sweep_prologue(a, NBR, ptab);
 
     const int tpp = d.tpp;
@@ -643,6 +645,35 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
 }
 
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+// Site of this thread in a single-lattice sweep (layout of SweepLayout); false if the
+// thread has none (past the last pixel, or outside the lattice in an edge tile).  All
+// threads of a pixel are consecutive lanes starting at a multiple of tpp.
+__device__ __forceinline__ bool sweep_thread_site(const SweepArgs &a, int tpp, int &pix, int &r, int &c, int &grp)
+{
+    const int64_t blk = a.blk0 + blockIdx.x;
+    const int t = (int)threadIdx.x;
+    if (a.patch >= 0) {
+        const int lp = 6 - a.patch, lr = lp >> 1, lc = lp - lr;
+        const int b = (int)blk;  // fewer than 2^31 workgroups
+        const int tr = b / a.tiles_w, tc = b - tr * a.tiles_w;
+        const int w = t >> 6;               // wave of the workgroup: 2x2 patches
+        const int p = (t & 63) >> a.patch;  // pixel within the wave's patch
+        grp = t & (tpp - 1);
+        r = (((tr << 1) + (w >> 1)) << lr) + (p >> lc);
+        c = (((tc << 1) + (w & 1)) << lc) + (p & ((1 << lc) - 1));
+        if (r >= a.H || c >= a.W) return false;
+        pix = r * a.W + c;
+        return true;
+    }
+    const int64_t gid = blk * kBlock + t;
+    if (gid >= (int64_t)a.H * a.W * tpp) return false;
+    pix = (int)(gid / tpp);
+    grp = (int)(gid - (int64_t)pix * tpp);
+    r = pix / a.W;
+    c = pix - r * a.W;
+    return true;
+}
 
 // Waves per SIMD the single-lattice sweep kernels are compiled for.  With 16-level blocks
 // (L > 16) the register allocator would otherwise settle at 127 VGPRs and 4 waves; at 5

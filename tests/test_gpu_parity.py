@@ -203,24 +203,33 @@ def test_many_chains_per_pixel(orc, C):
     assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
 
 
-def test_sweeps_larger_than_one_launch(orc):
-    """16384 x 16400 pixels with 64 chains: 4.3e9 threads per sweep, more than one dispatch
-    can count, so each sweep is issued as three launches (the last one ragged).  Chains 0-3
-    must equal an unsplit run with 4 chains everywhere, that run must equal the CPU
-    reference at sampled sites around the launch boundaries, and the mean accumulator must
-    hold the per-pixel sum of the new state over all 64 chains."""
+@pytest.mark.parametrize("L,C", [(2, 64), (32, 32)])
+def test_sweeps_larger_than_one_launch(orc, L, C):
+    """16384 x 16400 pixels whose sweep needs more workgroups than one launch may hold
+    (2^23 of 256 threads), so each sweep is issued as several launches with the last one
+    ragged: L = 2 with 64 chains (row-major order, 16.8e6 workgroups, three launches) and
+    L = 32 with 32 chains (2 x 4 pixel patches, 8.4e6 workgroups, two launches).  The
+    first four chains must equal an unsplit run with 4 chains everywhere, that run must
+    equal the CPU reference at sampled sites around the launch boundaries, and the mean
+    accumulator must hold the per-pixel sum of the new state over all chains."""
     torch = torch_cuda()
     H, W = 16384, 16400
-    rng = np.random.default_rng(8)
+    rng = np.random.default_rng(8 + L)
     yy = np.arange(H, dtype=np.int32)[:, None]
     xx = np.arange(W, dtype=np.int32)[None, :]
-    obs = np.where(((yy // 512) + (xx // 640)) % 2 == 0, np.float32(1.0), np.float32(-1.0))
-    obs += np.float32(0.6) * rng.standard_normal((H, W), dtype=np.float32)
-    kw = dict(height=H, width=W, levels=2, neighbourhood=4, prior=0, trunc=1, J=0.8, q=2.0, sigma=0.6, vmin=-1.0,
-              vmax=1.0, seed=1616, burn_in=0, tally_stride=0)
-    big = gpu_sampler(obs, chains=64, **kw).sweep(1)
+    lo, hi = (-1.0, 1.0) if L == 2 else (0.0, float(L - 1))
+    mid, amp = (lo + hi) / 2, (hi - lo) / 2
+    obs = np.where(((yy // 512) + (xx // 640)) % 2 == 0, np.float32(mid + amp), np.float32(mid - amp))
+    obs += np.float32(0.3 * amp) * rng.standard_normal((H, W), dtype=np.float32)
+    if L == 2:
+        model = dict(prior=0, trunc=1, J=0.8, q=2.0, sigma=0.6)
+    else:
+        model = dict(prior=1, trunc=4, J=0.3, q=1.0, sigma=0.3 * amp)
+    kw = dict(height=H, width=W, levels=L, neighbourhood=4, vmin=lo, vmax=hi, seed=1616 + L, burn_in=0,
+              tally_stride=0, **model)
+    big = gpu_sampler(obs, chains=C, **kw).sweep(1)
     small = gpu_sampler(obs, chains=4, **kw).sweep(1)
-    assert big.stats() == (1, 64, 0)
+    assert big.stats() == (1, C, 0)
     sb = big.state()
     ss = small.state()
     assert torch.equal(sb[:4], ss)
@@ -229,8 +238,12 @@ def test_sweeps_larger_than_one_launch(orc):
     del sb, acc
     big.close()
     N = H * W
-    split = [(1 << 31) // 16, (1 << 32) // 16]  # first pixels of the second and third launch
-    pix = np.concatenate([[0, W - 1, N - W, N - 1], [p + d for p in split for d in (-W, -1, 0, 1, W)],
+    if L == 2:  # row-major: first pixels of the second and third launch
+        split = [(1 << 31) // 16, (1 << 32) // 16]
+    else:  # 4 x 8 pixel tiles, 2050 per tile row: first tile of the second launch
+        t = 1 << 23
+        split = [(t // 2050) * 4 * W + (t % 2050) * 8]
+    pix = np.concatenate([[0, W - 1, N - W, N - 1], [p + d for p in split for d in (-W - 1, -1, 0, 1, W, W + 1)],
                           rng.integers(0, N, size=3000)]).astype(np.int64)
     chains = rng.integers(0, 4, size=pix.shape[0]).astype(np.int32)
     p4 = orc.Params(chains=4, **kw)
