@@ -45,8 +45,8 @@ struct SweepArgs {
 // the four waves of a workgroup a 2x2 arrangement of patches: the chains of nearby pixels
 // have similar neighbour levels, so more 16-level blocks pass the wave-wide far test
 // (measured on 2048x2048, L = 256, 16 chains: 2.79 against 2.94 ms per sweep).  Without
-// that test (L <= 16, L1/L2 inertia) row-major order was as fast or faster, and it is the
-// only order for other thread counts.
+// that test (L <= 16) row-major order was as fast or faster, and it is the only order for
+// other thread counts.
 struct SweepLayout {
     int patch;       // log2(threads per pixel), or -1 for row-major
     int tiles_w;     // tiles per row (patch layout)

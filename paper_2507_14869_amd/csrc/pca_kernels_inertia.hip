@@ -20,7 +20,7 @@ __global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel_inertia(S
 template <int G, int NBR>
 hipError_t launch_g(const SweepArgs &a0, hipStream_t s)
 {
-    const SweepLayout lay = sweep_layout(a0.H, a0.W, a0.Cp / G, false);
+    const SweepLayout lay = sweep_layout(a0.H, a0.W, a0.Cp / G, a0.L > 16);
     SweepArgs a = a0;
     a.patch = lay.patch;
     a.tiles_w = lay.tiles_w;

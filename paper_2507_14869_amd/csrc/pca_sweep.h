@@ -383,16 +383,33 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         for (int b = 0; b < NBLK; ++b) {
             if (b < nblk) {
                 const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
-                for (int i = 0; i < kend; ++i) {
-                    const int k = b * SUB + i;
-                    const float e = gp - (float)k;
-                    const float ee = e * e;
+                const bool lane_far = b * SUB + kend - 1 < nlo || b * SUB > nhi;
+                if (__all(lane_far)) {
+                    // every chain of the wave is at least T from all its neighbours here
+                    const float pfar = ptab[npres * a.T];
+                    for (int i = 0; i < kend; ++i) {
+                        const int k = b * SUB + i;
+                        const float e = gp - (float)k;
+                        const float ee = e * e;
 #pragma unroll
-                    for (int ch = 0; ch < G; ++ch) {
-                        const float E = exp2s(inertia_exponent(ee, k, xs[ch], a.inertia, a2, kc.q2) - fmx[ch]);
-                        acc[ch] = __builtin_fmaf(E, prior_lookup<NW>(pt, nb[ch], kk), acc[ch]);
+                        for (int ch = 0; ch < G; ++ch) {
+                            const float E = exp2s(inertia_exponent(ee, k, xs[ch], a.inertia, a2, kc.q2) - fmx[ch]);
+                            acc[ch] = __builtin_fmaf(E, pfar, acc[ch]);
+                        }
                     }
-                    kk += 0x01010101u;
+                    kk += (uint32_t)kend * 0x01010101u;
+                } else {
+                    for (int i = 0; i < kend; ++i) {
+                        const int k = b * SUB + i;
+                        const float e = gp - (float)k;
+                        const float ee = e * e;
+#pragma unroll
+                        for (int ch = 0; ch < G; ++ch) {
+                            const float E = exp2s(inertia_exponent(ee, k, xs[ch], a.inertia, a2, kc.q2) - fmx[ch]);
+                            acc[ch] = __builtin_fmaf(E, prior_lookup<NW>(pt, nb[ch], kk), acc[ch]);
+                        }
+                        kk += 0x01010101u;
+                    }
                 }
 #pragma unroll
                 for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
