@@ -370,6 +370,20 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         acc[ch] = stay[ch];
     }
 
+    // Levels below flo are below nlo for every lane of the wave, levels above fhi above
+    // every lane's nhi: there every chain's statistic is npres*T (the lane's own npres), so
+    // the prior factor is the table entry pfar.  Both bounds are wave-uniform, found by
+    // binary search with wave votes over the active lanes (the predicates are monotone).
+    int flo = 0, fhi = L - 1;
+    if constexpr (SUB > 1) {
+#pragma unroll
+        for (int step = 256; step >= 1; step >>= 1) {
+            if (flo + step <= L && __all(flo + step <= nlo)) flo += step;
+            if (fhi - step >= -1 && __all(nhi <= fhi - step)) fhi -= step;
+        }
+    }
+    const float pfar = ptab[npres * a.T];
+
     // Main pass over levels, keeping the running sum at the end of every block.  The
     // SHARE lanes serving one pixel each compute the data factor of every SHARE-th level
     // and broadcast it, so a pixel's chains share one evaluation per level.
@@ -383,10 +397,8 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         for (int b = 0; b < NBLK; ++b) {
             if (b < nblk) {
                 const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
-                const bool lane_far = b * SUB + kend - 1 < nlo || b * SUB > nhi;
-                if (__all(lane_far)) {
-                    // every chain of the wave is at least T from all its neighbours here
-                    const float pfar = ptab[npres * a.T];
+                // whole blocks only: a test per level in this loop measured slower
+                if (b * SUB + kend - 1 < flo || b * SUB > fhi) {  // wave-uniform: block far
                     for (int i = 0; i < kend; ++i) {
                         const int k = b * SUB + i;
                         const float e = gp - (float)k;
@@ -443,25 +455,19 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         for (int b = 0; b < NBLK; ++b) {
             if (b < nblk) {
                 const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
-                const bool lane_far = b * SUB + SUB - 1 < nlo || b * SUB > nhi;
-                if (kend == SUB && __all(lane_far)) {
-                    // the whole wave is far from its neighbours' levels in this block
-                    const float pfar = ptab[npres * a.T];
+                if (kend == SUB) {
 #pragma unroll 2
                     for (int i = 0; i < SUB; i += SHARE) {
+                        const int k = b * SUB + i;
                         const float e = gp - kq;
                         const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
                         kq += (float)SHARE;
-                        group_far<SHARE, 0, G>(acc, Dm, pfar);
-                    }
-                    kk += (uint32_t)SUB * 0x01010101u;
-                } else if (kend == SUB) {
-#pragma unroll 2
-                    for (int i = 0; i < SUB; i += SHARE) {
-                        const float e = gp - kq;
-                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
-                        kq += (float)SHARE;
-                        group_full<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk);
+                        if (k + SHARE - 1 < flo || k > fhi) {  // wave-uniform: all SHARE levels far
+                            group_far<SHARE, 0, G>(acc, Dm, pfar);
+                            kk += (uint32_t)SHARE * 0x01010101u;
+                        } else {
+                            group_full<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk);
+                        }
                     }
                 } else {
                     for (int i = 0; i < kend; i += SHARE) {
