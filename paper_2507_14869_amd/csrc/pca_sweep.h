@@ -455,19 +455,39 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         for (int b = 0; b < NBLK; ++b) {
             if (b < nblk) {
                 const int kend = (L - b * SUB) < SUB ? (L - b * SUB) : SUB;
-                if (kend == SUB) {
+                if (kend == SUB && SHARE == 4) {
+                    // groups of 4 levels tested against the wave-uniform far bounds
 #pragma unroll 2
                     for (int i = 0; i < SUB; i += SHARE) {
                         const int k = b * SUB + i;
                         const float e = gp - kq;
                         const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
                         kq += (float)SHARE;
-                        if (k + SHARE - 1 < flo || k > fhi) {  // wave-uniform: all SHARE levels far
+                        if (k + SHARE - 1 < flo || k > fhi) {
                             group_far<SHARE, 0, G>(acc, Dm, pfar);
                             kk += (uint32_t)SHARE * 0x01010101u;
                         } else {
                             group_full<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk);
                         }
+                    }
+                } else if (kend == SUB && (b * SUB + SUB - 1 < flo || b * SUB > fhi)) {
+                    // with fewer levels per group, whole blocks (a test per level or pair of
+                    // levels measured slower)
+#pragma unroll 2
+                    for (int i = 0; i < SUB; i += SHARE) {
+                        const float e = gp - kq;
+                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        kq += (float)SHARE;
+                        group_far<SHARE, 0, G>(acc, Dm, pfar);
+                    }
+                    kk += (uint32_t)SUB * 0x01010101u;
+                } else if (kend == SUB) {
+#pragma unroll 2
+                    for (int i = 0; i < SUB; i += SHARE) {
+                        const float e = gp - kq;
+                        const float Dm = exp2s(__builtin_fmaf(-a2, e * e, m));
+                        kq += (float)SHARE;
+                        group_full<SHARE, 0, G, NW>(pt, nb, acc, Dm, kk);
                     }
                 } else {
                     for (int i = 0; i < kend; i += SHARE) {
