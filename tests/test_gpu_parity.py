@@ -64,13 +64,15 @@ def test_stepwise_parity(orc, case):
     assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
 
 
+@pytest.mark.parametrize("L,C", [(7, 6), (40, 16)])
 @pytest.mark.parametrize("shape", [(1, 1), (1, 37), (29, 1), (2, 2), (3, 300), (257, 3)])
-def test_degenerate_lattices_free_running(orc, shape):
+def test_degenerate_lattices_free_running(orc, shape, L, C):
+    """Thin and tiny lattices, in row-major order (L = 7) and in 4x4-pixel patches of 8x8
+    tiles that the lattice fills only in part (L = 40, 16 chains)."""
     H, W = shape
-    L = 7
-    obs = _obs(H, W, L, seed=7 + H + W)
-    kw = dict(height=H, width=W, levels=L, chains=6, neighbourhood=8, prior=1, trunc=2, J=0.5, q=0.8, sigma=1.4,
-              vmin=0.0, vmax=6.0, seed=99, init_mode=1, tally_stride=1)
+    obs = _obs(H, W, L, seed=7 + H + W, sigma=0.2 * (L - 1))
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=8, prior=1, trunc=2 if L == 7 else 6, J=0.5,
+              q=0.8, sigma=1.4 if L == 7 else 8.0, vmin=0.0, vmax=float(L - 1), seed=99, init_mode=1, tally_stride=1)
     ref = oracle_run(orc, obs, **kw).sweep(12)
     gpu = gpu_sampler(obs, **kw).sweep(12)
     assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
