@@ -44,7 +44,7 @@ struct SweepArgs {
 // per pixel the pixels of a wave form a near-square patch (8x8, 4x8, 4x4, 2x4 or 2x2) and
 // the four waves of a workgroup a 2x2 arrangement of patches: the chains of nearby pixels
 // have similar neighbour levels, so more 16-level blocks pass the wave-wide far test
-// (measured on 2048x2048, L = 256, 16 chains: 2.79 against 2.94 ms per sweep).  Without
+// (measured on 2048x2048, L = 256, 16 chains: 2.76 against 2.94 ms per sweep).  Without
 // that test (L <= 16) row-major order was as fast or faster, and it is the only order for
 // other thread counts.
 struct SweepLayout {
