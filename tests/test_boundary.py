@@ -78,3 +78,15 @@ def test_null_observation_is_rejected(lib):
     with pytest.raises(_lib.PcaError) as e:
         _lib.pca_init(p, 0)
     assert e.value.code == _lib.PCA_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asked for more it exits with status 2 and says why,
+    before touching a device."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
+    assert r.stdout == ""
