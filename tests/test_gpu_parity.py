@@ -64,14 +64,15 @@ def test_stepwise_parity(orc, case):
     assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
 
 
-@pytest.mark.parametrize("L,C", [(7, 6), (40, 16)])
+@pytest.mark.parametrize("L,C,nbr", [(7, 6, 8), (40, 16, 8), (40, 16, 4), (40, 8, 4), (40, 4, 8)])
 @pytest.mark.parametrize("shape", [(1, 1), (1, 37), (29, 1), (2, 2), (3, 300), (257, 3)])
-def test_degenerate_lattices_free_running(orc, shape, L, C):
-    """Thin and tiny lattices, in row-major order (L = 7) and in 4x4-pixel patches of 8x8
-    tiles that the lattice fills only in part (L = 40, 16 chains)."""
+def test_degenerate_lattices_free_running(orc, shape, L, C, nbr):
+    """Thin and tiny lattices, in row-major order (L = 7) and in pixel patches that the
+    lattice fills only in part (L = 40): 4x4-pixel wave patches in 8x8 tiles (16 chains),
+    4x8 in 8x16 (8 chains) and 8x8 in 16x16 (4 chains)."""
     H, W = shape
     obs = _obs(H, W, L, seed=7 + H + W, sigma=0.2 * (L - 1))
-    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=8, prior=1, trunc=2 if L == 7 else 6, J=0.5,
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=nbr, prior=1, trunc=2 if L == 7 else 6, J=0.5,
               q=0.8, sigma=1.4 if L == 7 else 8.0, vmin=0.0, vmax=float(L - 1), seed=99, init_mode=1, tally_stride=1)
     ref = oracle_run(orc, obs, **kw).sweep(12)
     gpu = gpu_sampler(obs, **kw).sweep(12)
