@@ -43,7 +43,7 @@ typedef struct pca_ctx pca_ctx; /* opaque, library-owned */
 enum {
     PCA_OK = 0,
     PCA_EINVAL = -1,  /* invalid argument or parameter */
-    PCA_ENOMEM = -2,  /* device allocation failed */
+    PCA_ENOMEM = -2,  /* device (or host) allocation failed */
     PCA_EDEVICE = -3, /* HIP runtime or kernel error */
     PCA_ESTATE = -4,  /* operation not valid in the context's current state */
     PCA_EBUSY = -5    /* request refused by the server's load-shedding limit */
@@ -219,7 +219,8 @@ int pca_server_create(uint64_t hbm_budget_bytes, int32_t max_active, int32_t swe
  * [height][width] array (copied), and the number of sweeps to run.  *request_id receives
  * a positive id.  Errors: PCA_EINVAL (invalid parameters, a footprint above the whole
  * budget, or accumulators that could overflow), PCA_EBUSY (refused by the shedding limit,
- * see pca_server_set_shedding). */
+ * see pca_server_set_shedding), PCA_ENOMEM (the host copy could not be allocated; nothing
+ * was queued). */
 int pca_server_submit(pca_server *sv, const pca_params *params, const float *obs_host, int32_t sweeps,
                       int64_t *request_id);
 
@@ -233,8 +234,10 @@ int pca_server_set_shedding(pca_server *sv, double max_backlog_s);
 /* Number of submissions refused by the shedding limit so far. */
 int pca_server_shed_count(const pca_server *sv, int64_t *shed);
 
-/* One scheduling step on `stream` (synchronous: returns when the step's work is done).
- * *n_completed (may be NULL) receives the number of requests finished in this step. */
+/* One scheduling step on `stream` (synchronous: returns when the step's work is done,
+ * also on an error).  *n_completed (may be NULL) receives the number of requests finished
+ * in this step.  Errors: PCA_EDEVICE, PCA_ENOMEM (host memory for a finished request's
+ * results). */
 int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed);
 
 /* Ids of requests finished since the last call (at most `capacity`, oldest first). */

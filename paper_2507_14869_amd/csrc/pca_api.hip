@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -126,9 +127,15 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
     if (!obs_dev) return fail(PCA_EINVAL, "obs_dev is NULL");
     hipStream_t s = (hipStream_t)stream;
 
-    pca_ctx *ctx = new pca_ctx();
+    pca_ctx *ctx = new (std::nothrow) pca_ctx();
+    if (!ctx) return fail(PCA_ENOMEM, "host allocation failed");
     ctx->p = *params;
-    if (params->beta_len > 0) ctx->beta.assign(params->beta, params->beta + params->beta_len);
+    try {
+        if (params->beta_len > 0) ctx->beta.assign(params->beta, params->beta + params->beta_len);
+    } catch (const std::bad_alloc &) {
+        release(ctx);
+        return fail(PCA_ENOMEM, "host allocation failed");
+    }
     ctx->p.beta = nullptr;
     ctx->G = pcak::chain_group(params->chains);
     ctx->Cp = (params->chains + ctx->G - 1) / ctx->G * ctx->G;

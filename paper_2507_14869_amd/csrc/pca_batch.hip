@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <map>
+#include <new>
 #include <string>
 #include <vector>
 
@@ -286,21 +287,28 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
             return fail(PCA_EINVAL, "a batch cannot mix the indicator inertia with the L1/L2 norms");
     }
     hipStream_t s = (hipStream_t)stream;
-    pca_batch *b = new pca_batch();
+    pca_batch *b = new (std::nothrow) pca_batch();
+    if (!b) return fail(PCA_ENOMEM, "batch: host allocation failed");
     b->n = n;
     b->nbr = params[0].neighbourhood;
     b->inr = params[0].inertia != 0;
     b->last = s;
-    b->p.assign(params, params + n);
-    b->count.assign(n, 0);
-    b->tallies.assign(n, 0);
-    b->desc.resize(n);
     std::vector<double> betas;
-    std::vector<size_t> beta_off(n);
-    for (int i = 0; i < n; ++i) {
-        beta_off[i] = betas.size();
-        for (int j = 0; j < params[i].beta_len; ++j) betas.push_back((double)params[i].beta[j]);
-        b->p[i].beta = nullptr;
+    std::vector<size_t> beta_off;
+    try {
+        b->p.assign(params, params + n);
+        b->count.assign(n, 0);
+        b->tallies.assign(n, 0);
+        b->desc.resize(n);
+        beta_off.resize(n);
+        for (int i = 0; i < n; ++i) {
+            beta_off[i] = betas.size();
+            for (int j = 0; j < params[i].beta_len; ++j) betas.push_back((double)params[i].beta[j]);
+            b->p[i].beta = nullptr;
+        }
+    } catch (const std::bad_alloc &) {
+        release(b);
+        return fail(PCA_ENOMEM, "batch: host allocation failed");
     }
     hipError_t e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipMalloc(&b->d_desc, n * sizeof(pcak::ImageDesc));

@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <deque>
 #include <map>
+#include <new>
 #include <vector>
 
 #include "pca.h"
@@ -186,8 +187,13 @@ int read_out(Request *r, hipStream_t s)
     const pcak::ImageDesc &d = r->d;
     const int64_t N = (int64_t)d.H * d.W;
     const pca_params &p = r->p;
-    r->mean.resize((size_t)N);
-    r->state.resize((size_t)N * d.C);
+    try {
+        r->mean.resize((size_t)N);
+        r->state.resize((size_t)N * d.C);
+        if (d.hist && r->tallies > 0) r->mpm.resize((size_t)N);
+    } catch (const std::bad_alloc &) {
+        return fail(PCA_ENOMEM, "server: host allocation for the results failed");
+    }
     uint8_t *cur = (r->t & 1) ? d.x1 : d.x0;
     uint8_t *spare = (r->t & 1) ? d.x0 : d.x1;  // free now: holds [C][N] or [N] scratch
     float *mean_dev = const_cast<float *>(d.gp);  // the observation is no longer needed
@@ -202,7 +208,6 @@ int read_out(Request *r, hipStream_t s)
     if (e == hipSuccess) e = pcak::launch_get_state(cur, spare, N, d.C, d.Cp, s);
     if (e == hipSuccess) e = hipMemcpyAsync(r->state.data(), spare, (size_t)N * d.C, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess && d.hist && r->tallies > 0) {
-        r->mpm.resize((size_t)N);
         e = pcak::launch_mpm(d.hist, spare, N, d.L, d.hist_words, s);
         if (e == hipSuccess) e = hipMemcpyAsync(r->mpm.data(), spare, (size_t)N, hipMemcpyDeviceToHost, s);
     }
@@ -228,6 +233,14 @@ double backlog_units(const pca_server *sv)
 }
 
 // The two timing events of a step, destroyed on every return path.
+// Waits for the stream when a step returns, on every path, so that no copy the step
+// enqueued from host memory (its own vectors, the staging of admitted requests) is still
+// pending once the call has returned.
+struct StreamDrain {
+    hipStream_t s;
+    ~StreamDrain() { (void)hipStreamSynchronize(s); }
+};
+
 struct StepEvents {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool ok = false;
@@ -265,7 +278,8 @@ int pca_server_create(uint64_t hbm_budget_bytes, int32_t max_active, int32_t swe
     if (hbm_budget_bytes == 0 || max_active < 1 || max_active > 4096 || sweeps_per_step < 1 || !(step_ms > 0.0f))
         return fail(PCA_EINVAL, "need a positive budget, 1..4096 active requests, sweeps_per_step >= 1 and "
                                 "step_ms > 0");
-    pca_server *sv = new pca_server();
+    pca_server *sv = new (std::nothrow) pca_server();
+    if (!sv) return fail(PCA_ENOMEM, "server: host allocation failed");
     sv->budget = (size_t)hbm_budget_bytes;
     sv->max_active = max_active;
     sv->sweeps_per_step = sweeps_per_step;
@@ -300,16 +314,28 @@ int pca_server_submit(pca_server *sv, const pca_params *params, const float *obs
                         sv->max_backlog_s);
         }
     }
-    Request *r = new Request();
+    Request *r = new (std::nothrow) Request();
+    if (!r) return fail(PCA_ENOMEM, "server: host allocation failed");
     r->p = p;
-    if (p.beta_len > 0) r->beta.assign(p.beta, p.beta + p.beta_len);
     r->p.beta = nullptr;
     r->sweeps = sweeps;
     r->footprint = footprint_of(p);
-    r->obs.assign(obs_host, obs_host + (size_t)p.height * p.width);
-    r->id = sv->next_id++;
-    sv->queue.push_back(r);
-    sv->all[r->id] = r;
+    r->id = sv->next_id;
+    try {
+        if (p.beta_len > 0) r->beta.assign(p.beta, p.beta + p.beta_len);
+        r->obs.assign(obs_host, obs_host + (size_t)p.height * p.width);
+        sv->all[r->id] = r;
+        try {
+            sv->queue.push_back(r);
+        } catch (const std::bad_alloc &) {
+            sv->all.erase(r->id);
+            throw;
+        }
+    } catch (const std::bad_alloc &) {
+        delete r;
+        return fail(PCA_ENOMEM, "server: host allocation failed");
+    }
+    sv->next_id += 1;
     *request_id = r->id;
     return PCA_OK;
 }
@@ -335,6 +361,10 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     hipStream_t s = (hipStream_t)stream;
     sv->last = s;
     if (n_completed) *n_completed = 0;
+    std::vector<pcak::ImageDesc> desc;
+    std::vector<int> block_img;
+    std::vector<int> blocks_upto;  // blocks of the first j requests
+    const StreamDrain drain{s};    // declared after the vectors: runs before they are freed
     // 1. admission, first come first served, by device footprint and free slots (no
     //    synchronisation here: the uploads and initialisations are stream-ordered before
     //    the step's sweeps)
@@ -413,9 +443,6 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     // lay the requests out by decreasing sweep count, so launch i covers a prefix of the grid
     std::vector<Request *> launched(cand);
     std::stable_sort(launched.begin(), launched.end(), [&](Request *a, Request *b) { return k[a] > k[b]; });
-    std::vector<pcak::ImageDesc> desc;
-    std::vector<int> block_img;
-    std::vector<int> blocks_upto;  // blocks of the first j requests
     double units = 0.0;
     for (auto *r : launched) {
         pcak::ImageDesc d = r->d;
