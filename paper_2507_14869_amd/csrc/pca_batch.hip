@@ -117,7 +117,11 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
             blocks = (int)((threads + pcak::kBlock - 1) / pcak::kBlock);
         }
         if ((int64_t)base + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "batch grid exceeds 2^31 - 1 workgroups");
-        block_img.insert(block_img.end(), (size_t)blocks, i);
+        try {
+            block_img.insert(block_img.end(), (size_t)blocks, i);
+        } catch (const std::bad_alloc &) {
+            return fail(PCA_ENOMEM, "batch: host allocation failed");
+        }
         base += blocks;
     }
     (void)hipStreamSynchronize(b->last);  // no launch of the old layout may still be running
@@ -134,7 +138,10 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size() * sizeof(pcak::ImageDesc), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_fail(e, "batch: configuration upload");
+    if (e != hipSuccess) {
+        (void)hipStreamSynchronize(s);  // the first copy reads block_img, freed on return
+        return hip_fail(e, "batch: configuration upload");
+    }
     b->cfg = c;
     b->total_blocks = base;
     drop_graphs(b);
@@ -352,6 +359,7 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
         e = hipMemcpyAsync(b->d_beta, betas.data(), betas.size() * sizeof(double), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) {
+            (void)hipStreamSynchronize(s);  // the copy reads betas, freed on return
             release(b);
             return hip_fail(e, "batch: upload");
         }
