@@ -28,6 +28,11 @@
  *    on how sweeps are split across calls, on streams, or on other work on the device.
  *  - Layouts: images are row-major [height][width]; chain states are uint8 level
  *    indices, row-major [chains][height][width] at this boundary.
+ *  - Failure handling can be exercised from the host: the environment variable
+ *    PCA_FAULT_INJECT, read at every call, lists allocation sites that then fail as if
+ *    memory were exhausted ("init": pca_init's device buffers; "admit:<id>" / "readout:<id>":
+ *    a server request's device buffers at admission / host buffers for its results; a site
+ *    without ":<id>" fails for every request).  Unset, it changes nothing.
  */
 #ifndef PCA_MI355X_H
 #define PCA_MI355X_H
@@ -109,10 +114,12 @@ int pca_marginal_map(pca_ctx *ctx, uint8_t *out_dev, void *stream);
  * annealing, Sec. 6) to out_dev: device uint8 [chains][height][width]. */
 int pca_get_state(pca_ctx *ctx, uint8_t *out_dev, void *stream);
 
-/* Replaces the current states with in_dev (device uint8 [chains][height][width], every
- * value < levels; larger values are clamped to levels-1) and sets the sweep index to t >= 0.
- * Accumulators are kept.  Used to resume a run or to re-synchronise with another
- * implementation.  Errors: PCA_EINVAL. */
+/* Replaces the current states with in_dev (device uint8 [chains][height][width]) and sets
+ * the sweep index to t (0 <= t <= 2^32 - 1).  Accumulators are kept.  Used to resume a run
+ * or to re-synchronise with another implementation.  Every value must be a level index
+ * (< levels): the values are checked on the device first, so this call waits for
+ * `stream`.  Errors: PCA_EINVAL (NULL pointer, t out of range, or a value >= levels; the
+ * context is then unchanged), PCA_EDEVICE. */
 int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream);
 
 /* Reports the sweep index, the number of samples in the mean accumulator (chains times
@@ -235,23 +242,29 @@ int pca_server_set_shedding(pca_server *sv, double max_backlog_s);
 int pca_server_shed_count(const pca_server *sv, int64_t *shed);
 
 /* One scheduling step on `stream` (synchronous: returns when the step's work is done,
- * also on an error).  *n_completed (may be NULL) receives the number of requests finished
- * in this step.  Errors: PCA_EDEVICE, PCA_ENOMEM (host memory for a finished request's
- * results). */
+ * also on an error).  *n_completed (may be NULL) receives the number of requests that
+ * ended in this step, finished or failed.  The memory budget is the caller's estimate: if
+ * a request's device allocation fails at admission while other requests hold device
+ * memory, it waits at the head of the queue until they finish; if it fails with no other
+ * request admitted, it ends as failed (PCA_ENOMEM).  A request whose results cannot be
+ * copied to host memory also ends as failed.  The admitted requests advance either way.
+ * Errors: PCA_EDEVICE, PCA_ENOMEM (host memory for the step's own bookkeeping). */
 int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed);
 
 /* Ids of requests finished since the last call (at most `capacity`, oldest first). */
 int pca_server_completed(pca_server *sv, int64_t *ids, int32_t capacity, int32_t *n);
 
-/* status: 0 queued, 1 active, 2 finished; *sweep: sweeps done so far. */
+/* status: 0 queued, 1 active, 2 finished, 3 failed (pca_server_result returns its error);
+ * *sweep: sweeps done so far. */
 int pca_server_status(const pca_server *sv, int64_t id, int32_t *status, int64_t *sweep);
 
 /* Copies a finished request's posterior mean (float32 [H][W], value units), marginal mode
  * (uint8 [H][W]) and last states (uint8 [chains][H][W]) to host arrays; any may be NULL.
- * Errors: PCA_ESTATE if the request has not finished or the output does not exist. */
+ * Errors: PCA_ESTATE if the request has not finished or the output does not exist; for a
+ * failed request, the error that ended it (PCA_ENOMEM, PCA_EDEVICE). */
 int pca_server_result(pca_server *sv, int64_t id, float *mean_host, uint8_t *mpm_host, uint8_t *state_host);
 
-/* Forgets a finished request and its host results. */
+/* Forgets a finished or failed request and its host results. */
 int pca_server_release(pca_server *sv, int64_t id);
 
 /* Queue length, admitted requests, device bytes they hold, steps and sweeps launched. */

@@ -107,8 +107,12 @@ def lib():
         L.orc_constants.argtypes = [pp, ctypes.c_int64, ctypes.c_int32, f32]
         L.orc_draw.argtypes = [f32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]
         L.orc_draw.restype = ctypes.c_int32
+        L.orc_pca_rows.argtypes = [pp, f32, u8, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, u8]
+        L.orc_inertia_exponents.argtypes = [pp, f32, u8, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_int64, f32, f32]
         for name in ("orc_init_state", "orc_run", "orc_update_sites", "orc_site_acc",
-                     "orc_posterior_mean", "orc_marginal_map", "orc_constants"):
+                     "orc_posterior_mean", "orc_marginal_map", "orc_constants", "orc_pca_rows",
+                     "orc_inertia_exponents"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -233,6 +237,54 @@ def update_sites(p: Params, obs: np.ndarray, state: np.ndarray, t: int, chains: 
                                 _ptr(out, ctypes.c_uint8))
     _check(rc, "orc_update_sites")
     return out
+
+
+def pca_rows(p: Params, obs: np.ndarray, state: np.ndarray, t: int, chain: int, r0: int, r1: int) -> np.ndarray:
+    """New values of one chain after PCA sweep t for rows r0 .. r1-1, from the full
+    previous state [C][H][W] (the oracle's C code runs outside the interpreter lock, so
+    row bands may be computed in several threads)."""
+    b = _Bound(p)
+    obs = np.ascontiguousarray(obs, dtype=np.float32)
+    state = np.ascontiguousarray(state, dtype=np.uint8)
+    assert state.shape == (p.chains, p.height, p.width) and obs.shape == (p.height, p.width)
+    out = np.zeros((r1 - r0, p.width), dtype=np.uint8)
+    rc = lib().orc_pca_rows(b.ref, _ptr(obs, ctypes.c_float), _ptr(state, ctypes.c_uint8), int(t), int(chain),
+                            int(r0), int(r1), _ptr(out, ctypes.c_uint8))
+    _check(rc, "orc_pca_rows")
+    return out
+
+
+def pca_sweep_threaded(p: Params, obs: np.ndarray, state: np.ndarray, t: int, threads: int = 8,
+                       band: int = 64) -> np.ndarray:
+    """The whole next state [C][H][W] after PCA sweep t, computed in row bands of every
+    chain by a pool of host threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    obs = np.ascontiguousarray(obs, dtype=np.float32)
+    state = np.ascontiguousarray(state, dtype=np.uint8)
+    out = np.empty_like(state)
+    jobs = [(ch, r0, min(r0 + band, p.height)) for ch in range(p.chains) for r0 in range(0, p.height, band)]
+
+    def one(job):
+        ch, r0, r1 = job
+        out[ch, r0:r1] = pca_rows(p, obs, state, t, ch, r0, r1)
+
+    with ThreadPoolExecutor(max_workers=max(1, threads)) as pool:
+        list(pool.map(one, jobs))
+    return out
+
+
+def inertia_exponents(p: Params, obs: np.ndarray, state: np.ndarray, chain: int, r: int, c: int, t: int = 0):
+    """(F_0 .. F_{L-1}, Fmax): the unshifted L1/L2 exponents of one site and the O(1)
+    shift the sampler subtracts from them."""
+    b = _Bound(p)
+    obs = np.ascontiguousarray(obs, dtype=np.float32)
+    state = np.ascontiguousarray(state, dtype=np.uint8)
+    F = np.zeros(p.levels, dtype=np.float32)
+    fmax = np.zeros(1, dtype=np.float32)
+    rc = lib().orc_inertia_exponents(b.ref, _ptr(obs, ctypes.c_float), _ptr(state, ctypes.c_uint8), chain, r, c,
+                                     t, _ptr(F, ctypes.c_float), _ptr(fmax, ctypes.c_float))
+    _check(rc, "orc_inertia_exponents")
+    return F, float(fmax[0])
 
 
 def site_acc(p: Params, obs: np.ndarray, state: np.ndarray, chain: int, r: int, c: int, t: int = 0,

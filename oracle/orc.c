@@ -273,6 +273,27 @@ static float inertia_exponent(float gp, int k, int x, int p, float a2, float q2)
     return fmaf(-a2, e * e, -(q2 * (float)dp));
 }
 
+/* Shift of the C8 exponents: their maximum over the levels, found in O(1).  F_k is a
+ * concave function of k (a downward parabola in k plus -q2|k - x|^p, p >= 1), so its
+ * maximum over the integers lies at one of the two integers around the maximiser kc of
+ * the real-valued form: kc = clamp(x, g' - h, g' + h) with h = q2/(2 a2) for p = 1, the
+ * weighted mean (a2 g' + q2 x)/(a2 + q2) for p = 2. */
+static float inertia_fmax(const orc_run_consts *rc, const orc_sweep_consts *sc, float gp, int x)
+{
+    float kc;
+    if (sc->p == 1) {
+        float h = sc->q2 / (2.0f * rc->a2);
+        kc = fminf(fmaxf((float)x, gp - h), gp + h);
+    } else {
+        kc = (rc->a2 * gp + sc->q2 * (float)x) / (rc->a2 + sc->q2);
+    }
+    int k1 = (int)fminf(fmaxf(floorf(kc), 0.0f), (float)(rc->L - 1));
+    int k2 = k1 + 1 < rc->L ? k1 + 1 : k1;
+    float F1 = inertia_exponent(gp, k1, x, sc->p, rc->a2, sc->q2);
+    float F2 = inertia_exponent(gp, k2, x, sc->p, rc->a2, sc->q2);
+    return F1 > F2 ? F1 : F2;
+}
+
 /* S_k = sum over in-lattice neighbours j of min(|k - x_j|, T); `plane` is one chain's
  * [H][W] state. */
 static int neighbour_stat(const orc_run_consts *rc, const uint8_t *plane, int r, int c, int k)
@@ -297,18 +318,7 @@ static void site_acc(const orc_run_consts *rc, const orc_sweep_consts *sc, const
 {
     int x = plane[(size_t)r * rc->W + c];
     if (sc->p > 0) { /* C8: data and inertia in one shifted exponent, no stay branch */
-        float kc;
-        if (sc->p == 1) {
-            float h = sc->q2 / (2.0f * rc->a2);
-            kc = fminf(fmaxf((float)x, gp - h), gp + h);
-        } else {
-            kc = (rc->a2 * gp + sc->q2 * (float)x) / (rc->a2 + sc->q2);
-        }
-        int k1 = (int)fminf(fmaxf(floorf(kc), 0.0f), (float)(rc->L - 1));
-        int k2 = k1 + 1 < rc->L ? k1 + 1 : k1;
-        float F1 = inertia_exponent(gp, k1, x, sc->p, rc->a2, sc->q2);
-        float F2 = inertia_exponent(gp, k2, x, sc->p, rc->a2, sc->q2);
-        float Fmax = F1 > F2 ? F1 : F2;
+        float Fmax = inertia_fmax(rc, sc, gp, x);
         float a = 0.0f;
         acc[0] = a;
         for (int k = 0; k < rc->L; ++k) {
@@ -467,6 +477,55 @@ int orc_update_sites(const orc_params *p, const float *obs, const uint8_t *state
         out[s] = (uint8_t)draw_from_acc(scratch, rc.L, plane[pix], w);
     }
     free(scratch);
+    return ORC_OK;
+}
+
+/* New PCA values of one chain after sweep t, for rows r0 .. r1-1 of the lattice, from the
+ * full previous state ([C][H][W]); out is [r1-r0][W].  Row bands of one sweep can be
+ * computed independently (each reads only the previous state), so a whole sweep of a
+ * large lattice can be checked band by band, in several host threads. */
+int orc_pca_rows(const orc_params *p, const float *obs, const uint8_t *state, int64_t t, int32_t chain,
+                 int32_t r0, int32_t r1, uint8_t *out)
+{
+    int rcode = check_params(p);
+    if (rcode) return rcode;
+    orc_run_consts rc = run_consts(p);
+    if (chain < 0 || chain >= rc.C || r0 < 0 || r1 > rc.H || r0 > r1 || t < 0) return ORC_EINVAL;
+    size_t N = (size_t)rc.H * rc.W;
+    float *scratch = (float *)malloc((size_t)(rc.L + 1) * sizeof(float));
+    if (!scratch) return ORC_ENOMEM;
+    orc_sweep_consts sc = sweep_consts(p, t, 0);
+    const uint8_t *plane = state + (size_t)chain * N;
+    for (int r = r0; r < r1; ++r) {
+        for (int c = 0; c < rc.W; ++c) {
+            size_t pix = (size_t)r * rc.W + c;
+            float gp = (float)(((double)obs[pix] - (double)p->vmin) * rc.scale);
+            site_acc(&rc, &sc, plane, r, c, gp, scratch);
+            uint32_t w = chain_word(p->seed, (uint32_t)pix, (uint32_t)t, chain, 0);
+            out[(size_t)(r - r0) * rc.W + c] = (uint8_t)draw_from_acc(scratch, rc.L, plane[pix], w);
+        }
+    }
+    free(scratch);
+    return ORC_OK;
+}
+
+/* The C8 exponents F_0 .. F_{L-1} of one site (unshifted) and the O(1) shift Fmax the
+ * sampler uses, for tests that compare the shift with the plain maximum over the levels. */
+int orc_inertia_exponents(const orc_params *p, const float *obs, const uint8_t *state, int32_t chain,
+                          int32_t r, int32_t c, int64_t t, float *F, float *Fmax)
+{
+    int rcode = check_params(p);
+    if (rcode) return rcode;
+    if (p->inertia < 1) return ORC_EINVAL;
+    orc_run_consts rc = run_consts(p);
+    if (chain < 0 || chain >= rc.C || r < 0 || r >= rc.H || c < 0 || c >= rc.W) return ORC_EINVAL;
+    size_t N = (size_t)rc.H * rc.W;
+    orc_sweep_consts sc = sweep_consts(p, t, 0);
+    size_t pix = (size_t)r * rc.W + c;
+    float gp = (float)(((double)obs[pix] - (double)p->vmin) * rc.scale);
+    int x = state[(size_t)chain * N + pix];
+    for (int k = 0; k < rc.L; ++k) F[k] = inertia_exponent(gp, k, x, sc.p, rc.a2, sc.q2);
+    *Fmax = inertia_fmax(&rc, &sc, gp, x);
     return ORC_OK;
 }
 

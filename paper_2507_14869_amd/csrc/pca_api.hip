@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -26,6 +27,7 @@ struct pca_ctx {
     int cur = 0;
     uint32_t *sum = nullptr;
     uint32_t *hist = nullptr;
+    int *flag = nullptr;  // device word for pca_set_state's level check
     int64_t t = 0, count = 0, tallies = 0;
     hipStream_t last = nullptr;
 };
@@ -94,6 +96,7 @@ void release(pca_ctx *ctx)
     (void)hipFree(ctx->x[1]);
     (void)hipFree(ctx->sum);
     (void)hipFree(ctx->hist);
+    (void)hipFree(ctx->flag);
     delete ctx;
 }
 
@@ -111,6 +114,28 @@ int pcak::set_error(int code, const char *message)
 {
     g_err = message;
     return code;
+}
+
+bool pcak::fault_injected(const char *site, int64_t id)
+{
+    const char *spec = std::getenv("PCA_FAULT_INJECT");
+    if (!spec || !*spec) return false;
+    const size_t n = std::strlen(site);
+    for (const char *p = spec; *p;) {
+        const char *end = std::strchr(p, ',');
+        if (!end) end = p + std::strlen(p);
+        if ((size_t)(end - p) >= n && std::strncmp(p, site, n) == 0) {
+            const char *rest = p + n;
+            if (rest == end) return true;  // every call at this site
+            if (*rest == ':') {
+                char *stop = nullptr;
+                const long long want = std::strtoll(rest + 1, &stop, 10);
+                if (stop == end && want == (long long)id) return true;
+            }
+        }
+        p = *end ? end + 1 : end;
+    }
+    return false;
 }
 
 extern "C" {
@@ -146,7 +171,8 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
     ctx->last = s;
 
     const size_t N = (size_t)ctx->N;
-    hipError_t e = hipMalloc(&ctx->gp, N * sizeof(float));
+    hipError_t e = pcak::fault_injected("init", 0) ? hipErrorOutOfMemory : hipMalloc(&ctx->gp, N * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&ctx->flag, sizeof(int));
     if (e == hipSuccess) e = hipMalloc(&ctx->x[0], N * ctx->Cp);
     if (e == hipSuccess) e = hipMalloc(&ctx->x[1], N * ctx->Cp);
     if (e == hipSuccess) e = hipMalloc(&ctx->sum, N * sizeof(uint32_t));
@@ -289,7 +315,15 @@ int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream)
     if (t < 0 || t > 0xFFFFFFFFll) return fail(PCA_EINVAL, "t out of range");
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
-    hipError_t e = pcak::launch_set_state(in_dev, ctx->x[ctx->cur], ctx->N, ctx->p.chains, ctx->Cp, ctx->p.levels, s);
+    // every value must be a level index: checked on the device, then read back
+    int bad = 0;
+    hipError_t e = hipMemsetAsync(ctx->flag, 0, sizeof(int), s);
+    if (e == hipSuccess) e = pcak::launch_check_levels(in_dev, ctx->N * ctx->p.chains, ctx->p.levels, ctx->flag, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, ctx->flag, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "pca_set_state");
+    if (bad) return fail(PCA_EINVAL, "pca_set_state: a state value is not below levels (%d)", ctx->p.levels);
+    e = pcak::launch_set_state(in_dev, ctx->x[ctx->cur], ctx->N, ctx->p.chains, ctx->Cp, s);
     if (e != hipSuccess) return hip_fail(e, "pca_set_state");
     ctx->t = t;
     return PCA_OK;

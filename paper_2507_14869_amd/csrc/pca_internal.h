@@ -142,10 +142,20 @@ hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int blocks, int G, i
 int validate_params(const pca_params *p);     // PCA_OK or PCA_EINVAL with the error message set
 int set_error(int code, const char *message);  // records the calling thread's last error, returns code
 
+// Failure-handling hook for tests: the environment variable PCA_FAULT_INJECT holds a
+// comma-separated list of allocation sites, each optionally with a request id
+// ("init", "admit:3", "readout:7").  A listed site fails as if its allocation had been
+// refused: "init" the device buffers of pca_init, "admit" a server request's device
+// buffers at admission, "readout" the host buffers of a finished request's results.
+// The variable is read at every call, so a test can set and clear it between calls.
+bool fault_injected(const char *site, int64_t id);
+
 hipError_t launch_init(const InitArgs &a, hipStream_t s);
 hipError_t launch_sweep(const SweepArgs &a, int G, int nbr, hipStream_t s);
 hipError_t launch_get_state(const uint8_t *x, uint8_t *out, int64_t N, int C, int Cp, hipStream_t s);
-hipError_t launch_set_state(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp, int L, hipStream_t s);
+hipError_t launch_set_state(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp, hipStream_t s);
+// Sets *flag (device int, zeroed by the caller) to 1 if any of the n bytes at in is >= L.
+hipError_t launch_check_levels(const uint8_t *in, int64_t n, int L, int *flag, hipStream_t s);
 hipError_t launch_mean(const uint32_t *sum, float *out, int64_t N, int64_t count, double vmin, double delta,
                        hipStream_t s);
 hipError_t launch_mpm(const uint32_t *hist, uint8_t *out, int64_t N, int L, int hist_words, hipStream_t s);

@@ -54,16 +54,26 @@ __global__ __launch_bounds__(kBlock) void get_state_kernel(const uint8_t *x, uin
     for (int ch = 0; ch < C; ++ch) out[(int64_t)ch * N + pix] = x[pix * Cp + ch];
 }
 
-__global__ __launch_bounds__(kBlock) void set_state_kernel(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp,
-                                                           int L)
+// Padding chain slots (ch >= C) take chain 0's value: they are never read out, and any
+// valid level keeps their (discarded) draws in range.
+__global__ __launch_bounds__(kBlock) void set_state_kernel(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp)
 {
     const int64_t pix = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (pix >= N) return;
     for (int ch = 0; ch < Cp; ++ch) {
         const int src = ch < C ? ch : 0;
-        const int v = in[(int64_t)src * N + pix];
-        x[pix * Cp + ch] = (uint8_t)(v < L ? v : L - 1);
+        x[pix * Cp + ch] = in[(int64_t)src * N + pix];
     }
+}
+
+constexpr int kCheckBlocks = 2048;
+
+__global__ __launch_bounds__(kBlock) void check_levels_kernel(const uint8_t *in, int64_t n, int L, int *flag)
+{
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)kCheckBlocks * kBlock)
+        bad = bad || (int)in[i] >= L;
+    if (bad) atomicOr(flag, 1);
 }
 
 __global__ __launch_bounds__(kBlock) void mean_kernel(const uint32_t *sum, float *out, int64_t N, int64_t count,
@@ -166,9 +176,15 @@ hipError_t launch_get_state(const uint8_t *x, uint8_t *out, int64_t N, int C, in
     return hipGetLastError();
 }
 
-hipError_t launch_set_state(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp, int L, hipStream_t s)
+hipError_t launch_set_state(const uint8_t *in, uint8_t *x, int64_t N, int C, int Cp, hipStream_t s)
 {
-    hipLaunchKernelGGL(set_state_kernel, dim3(grid_for(N)), dim3(kBlock), 0, s, in, x, N, C, Cp, L);
+    hipLaunchKernelGGL(set_state_kernel, dim3(grid_for(N)), dim3(kBlock), 0, s, in, x, N, C, Cp);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_levels(const uint8_t *in, int64_t n, int L, int *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_levels_kernel, dim3(kCheckBlocks), dim3(kBlock), 0, s, in, n, L, flag);
     return hipGetLastError();
 }
 

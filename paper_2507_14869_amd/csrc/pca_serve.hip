@@ -16,6 +16,7 @@
 #include <deque>
 #include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "pca.h"
@@ -37,7 +38,7 @@ int hip_fail(hipError_t e, const char *what) { return fail(PCA_EDEVICE, "%s: %s"
 
 double level_scale(const pca_params &p) { return (double)(p.levels - 1) / ((double)p.vmax - (double)p.vmin); }
 
-enum { QUEUED = 0, ACTIVE = 1, DONE = 2 };
+enum { QUEUED = 0, ACTIVE = 1, DONE = 2, FAILED = 3 };
 
 struct Request {
     int64_t id = 0;
@@ -52,6 +53,8 @@ struct Request {
     float *d_obs = nullptr;
     int64_t t = 0, count = 0, tallies = 0;
     int status = QUEUED;
+    int err_code = PCA_OK;  // FAILED: the error that ended the request, and its message
+    std::string err_msg;
     std::vector<float> mean;
     std::vector<uint8_t> mpm, state;
 };
@@ -134,7 +137,7 @@ int admit(pca_server *sv, Request *r, hipStream_t s)
     d.beta_len = (int)r->beta.size();
     const size_t N = (size_t)d.H * d.W;
     float *gp = nullptr;
-    hipError_t e = hipMalloc(&gp, N * sizeof(float));
+    hipError_t e = pcak::fault_injected("admit", r->id) ? hipErrorOutOfMemory : hipMalloc(&gp, N * sizeof(float));
     d.gp = gp;
     if (e == hipSuccess) e = hipMalloc(&r->d_obs, N * sizeof(float));
     if (e == hipSuccess) e = hipMalloc(&d.x0, N * d.Cp);
@@ -187,6 +190,8 @@ int read_out(Request *r, hipStream_t s)
     const pcak::ImageDesc &d = r->d;
     const int64_t N = (int64_t)d.H * d.W;
     const pca_params &p = r->p;
+    if (pcak::fault_injected("readout", r->id))
+        return fail(PCA_ENOMEM, "server: host allocation for the results of request %lld failed", (long long)r->id);
     try {
         r->mean.resize((size_t)N);
         r->state.resize((size_t)N * d.C);
@@ -223,6 +228,11 @@ void release_staging(Request *r)
     r->d_obs = nullptr;
 }
 
+// Ends a request with an error: its device memory (if any) is released, its host copies
+// dropped, and it is reported among the completed requests with status FAILED;
+// pca_server_result then returns the error.
+void fail_request(pca_server *sv, Request *r, int code, const char *msg);
+
 // Remaining work of the accepted requests (admitted and queued), in cost-model units.
 double backlog_units(const pca_server *sv)
 {
@@ -251,6 +261,27 @@ struct StepEvents {
         if (e1) (void)hipEventDestroy(e1);
     }
 };
+
+void fail_request(pca_server *sv, Request *r, int code, const char *msg)
+{
+    free_device(r);
+    if (r->status == ACTIVE) sv->used -= r->footprint;
+    r->status = FAILED;
+    r->err_code = code;
+    try {
+        r->err_msg = msg;
+    } catch (const std::bad_alloc &) {
+    }
+    std::vector<float>().swap(r->obs);
+    std::vector<double>().swap(r->beta_d);
+    std::vector<float>().swap(r->mean);
+    std::vector<uint8_t>().swap(r->mpm);
+    std::vector<uint8_t>().swap(r->state);
+    try {
+        sv->completed.push_back(r->id);
+    } catch (const std::bad_alloc &) {
+    }
+}
 
 int ensure_capacity(pca_server *sv, size_t blocks)
 {
@@ -367,16 +398,35 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     const StreamDrain drain{s};    // declared after the vectors: runs before they are freed
     // 1. admission, first come first served, by device footprint and free slots (no
     //    synchronisation here: the uploads and initialisations are stream-ordered before
-    //    the step's sweeps)
+    //    the step's sweeps).  The budget is the caller's; the device may hold less.  If a
+    //    request's allocation fails while others hold device memory, it stays at the head
+    //    of the queue until they finish; if it fails with nothing else admitted, waiting
+    //    cannot help and the request fails.  Either way the admitted requests advance.
     std::vector<Request *> admitted;
     while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active &&
            sv->used + sv->queue.front()->footprint <= sv->budget) {
         Request *r = sv->queue.front();
         int rc = admit(sv, r, s);
-        if (rc) return rc;
+        if (rc != PCA_OK) {
+            if (!sv->active.empty()) break;
+            sv->queue.pop_front();
+            fail_request(sv, r, rc, pca_last_error());
+            continue;
+        }
         sv->queue.pop_front();
         sv->active.push_back(r);
         admitted.push_back(r);
+    }
+    // a request that reached its sweep count in a step that then failed (a device error
+    // before its results were safely on the host) cannot be read out again
+    for (size_t i = 0; i < sv->active.size();) {
+        Request *r = sv->active[i];
+        if (r->t < r->sweeps) {
+            ++i;
+            continue;
+        }
+        sv->active.erase(sv->active.begin() + (std::ptrdiff_t)i);
+        fail_request(sv, r, PCA_EDEVICE, "an earlier step failed before this request's results were read out");
     }
     if (sv->active.empty()) return PCA_OK;
     // 2. sweeps per request this step: at least one each, then the rest of the step's
@@ -386,8 +436,9 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     const int nbr = sv->active.front()->p.neighbourhood;
     const bool inr = sv->active.front()->p.inertia != 0;
     std::vector<Request *> cand;
-    for (auto *r : sv->active)
-        if (r->p.neighbourhood == nbr && (r->p.inertia != 0) == inr) cand.push_back(r);
+    for (auto *r : sv->active)  // an active request has sweeps left: it finishes in the step that ends them
+        if (r->p.neighbourhood == nbr && (r->p.inertia != 0) == inr && r->t < r->sweeps) cand.push_back(r);
+    if (cand.empty()) return PCA_OK;
     if (cand.size() < sv->active.size())
         std::rotate(sv->active.begin(), sv->active.begin() + 1, sv->active.end());
     std::map<Request *, int64_t> k;
@@ -477,8 +528,11 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     if (e != hipSuccess) return hip_fail(e, "server: sweep launch");
     sv->steps += 1;
     sv->sweeps_launched += K;
-    // 3. bookkeeping of the sweeps each request took, read-out of finished requests
+    // 3. bookkeeping of the sweeps each request took, read-out of finished requests; a
+    //    request whose read-out fails ends with that error (its device memory is released
+    //    after the step's synchronisation, like a finished request's)
     std::vector<Request *> finished;
+    std::vector<std::pair<Request *, std::pair<int, std::string>>> broken;
     for (auto *r : launched) {
         const int64_t adv = k[r];
         int64_t sweeps = 0, tallies = 0;
@@ -488,8 +542,12 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         r->t += adv;
         if (r->t >= r->sweeps) {
             rc = read_out(r, s);
-            if (rc) return rc;
-            finished.push_back(r);
+            try {
+                if (rc == PCA_OK) finished.push_back(r);
+                else broken.push_back({r, {rc, std::string(pca_last_error())}});
+            } catch (const std::bad_alloc &) {
+                return fail(PCA_ENOMEM, "server: host allocation failed");
+            }
         }
     }
     // the host vectors above are filled by asynchronous copies; the descriptor and block
@@ -509,7 +567,11 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         sv->active.erase(std::find(sv->active.begin(), sv->active.end(), r));
         sv->completed.push_back(r->id);
     }
-    if (n_completed) *n_completed = (int32_t)finished.size();
+    for (auto &b : broken) {
+        sv->active.erase(std::find(sv->active.begin(), sv->active.end(), b.first));
+        fail_request(sv, b.first, b.second.first, b.second.second.c_str());
+    }
+    if (n_completed) *n_completed = (int32_t)(finished.size() + broken.size());
     return PCA_OK;
 }
 
@@ -539,6 +601,8 @@ int pca_server_result(pca_server *sv, int64_t id, float *mean_host, uint8_t *mpm
     auto it = sv->all.find(id);
     if (it == sv->all.end()) return fail(PCA_EINVAL, "unknown request %lld", (long long)id);
     Request *r = it->second;
+    if (r->status == FAILED)
+        return fail(r->err_code, "request %lld failed: %s", (long long)id, r->err_msg.c_str());
     if (r->status != DONE) return fail(PCA_ESTATE, "request %lld has not finished", (long long)id);
     if (mean_host && r->count <= 0) return fail(PCA_ESTATE, "request %lld accumulated no sweeps", (long long)id);
     if (mpm_host && r->mpm.empty()) return fail(PCA_ESTATE, "request %lld has no histogram", (long long)id);
@@ -553,7 +617,8 @@ int pca_server_release(pca_server *sv, int64_t id)
     if (!sv) return fail(PCA_EINVAL, "server is NULL");
     auto it = sv->all.find(id);
     if (it == sv->all.end()) return fail(PCA_EINVAL, "unknown request %lld", (long long)id);
-    if (it->second->status != DONE) return fail(PCA_ESTATE, "request %lld has not finished", (long long)id);
+    if (it->second->status != DONE && it->second->status != FAILED)
+        return fail(PCA_ESTATE, "request %lld has not finished", (long long)id);
     delete it->second;
     sv->all.erase(it);
     return PCA_OK;

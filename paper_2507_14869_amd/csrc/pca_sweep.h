@@ -648,7 +648,7 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
     a.Cp = d.Cp;
     a.T = d.T;
     a.hist_words = d.hist_words;
-    a.beta = d.beta_len == 0 ? 1.0 : d.beta[(int)t < d.beta_len ? (int)t : d.beta_len - 1];
+    a.beta = d.beta_len == 0 ? 1.0 : d.beta[t < (uint32_t)d.beta_len ? t : (uint32_t)(d.beta_len - 1)];
     a.J = d.J;
     a.q = d.q;
     a.kappa = d.kappa;
@@ -676,6 +676,9 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
         const int th = kBlock / tpp / kTileW;  // tile height in pixels
         const int tr = local / d.tiles_w, tc = local - (local / d.tiles_w) * d.tiles_w;
         const int lp = (int)threadIdx.x / tpp;
+        // when tpp does not divide kBlock / kTileW, the last threads of the workgroup have
+        // no pixel in its tile (they would land in the next tile row)
+        if (lp >= th * kTileW) return;
         grp = (int)threadIdx.x - lp * tpp;
         r = tr * th + lp / kTileW;
         c = tc * kTileW + lp % kTileW;

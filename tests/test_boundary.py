@@ -90,3 +90,22 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+def test_injected_allocation_failure_in_init(lib, monkeypatch):
+    """The failure-handling hook: with PCA_FAULT_INJECT naming the "init" site, pca_init
+    fails as if device memory were exhausted (PCA_ENOMEM, no context), before any device
+    work; other sites and an unset variable change nothing."""
+    from paper_2507_14869_amd import _lib
+    p, _buf = _lib.make_params(height=4, width=4, levels=4, J=0.1, q=0.5, sigma=1.0)
+    for spec in ("init", "admit:3,init", "readout,init"):
+        monkeypatch.setenv("PCA_FAULT_INJECT", spec)
+        with pytest.raises(_lib.PcaError) as e:
+            _lib.pca_init(p, 0x1000)
+        assert e.value.code == _lib.PCA_ENOMEM
+        assert "allocation" in _lib.pca_last_error()
+    monkeypatch.setenv("PCA_FAULT_INJECT", "initx")  # not the init site: validation still comes first
+    bad, _b2 = _lib.make_params(height=4, width=4, levels=1)
+    with pytest.raises(_lib.PcaError) as e:
+        _lib.pca_init(bad, 0x1000)
+    assert e.value.code == _lib.PCA_EINVAL

@@ -160,3 +160,31 @@ def test_batch_with_inertia_norms(orc):
     with pytest.raises(PcaError):
         _batch([problems[0], _problem(16, 16, 16, 4, 35)])
     b.close()
+
+
+@pytest.mark.parametrize("chains,configs", [(12, [(4, 1, 1), (2, 2, 1), (1, 4, 1), (1, 2, 1)]),
+                                            (20, [(4, 1, 1), (2, 2, 1), (2, 1, 1)])])
+def test_tiled_batch_with_pixels_that_do_not_fill_a_tile(orc, chains, configs):
+    """Tiled traversal with 3, 5, 6, 10 or 12 threads per pixel: 256 threads then hold
+    fewer than a whole number of 16-pixel tile rows, and the threads left over must not
+    sweep pixels of the next tile (which would count them twice in the mean and the
+    histogram).  Each lattice equals itself run alone, and one equals the CPU reference."""
+    problems = [_problem(*spec, seed=60 + i) for i, spec in enumerate([(29, 37, 16, chains), (40, 21, 256, chains),
+                                                                       (17, 33, 2, chains)])]
+    for config in configs:
+        b = _batch(problems)
+        b.set_config(*config)
+        assert b.config == config
+        b.sweep(3).sweep(4)
+        for i, (obs, kw) in enumerate(problems):
+            ref = _alone(obs, kw, 7)
+            assert np.array_equal(b.state(i).cpu().numpy(), ref.state().cpu().numpy()), (config, i)
+            assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean().cpu().numpy()), (config, i)
+            assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map().cpu().numpy()), (config, i)
+            assert b.stats(i) == ref.stats()
+            ref.close()
+        obs, kw = problems[0]
+        want = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(7)
+        assert np.array_equal(b.posterior_mean(0).cpu().numpy(), want.posterior_mean())
+        assert np.array_equal(b.marginal_map(0).cpu().numpy(), want.marginal_map())
+        b.close()

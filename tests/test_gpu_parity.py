@@ -105,8 +105,9 @@ def test_value_units_and_random_init(orc):
     (2, 2, 9, (7, 13, 11, 40), 2),
 ])
 def test_deferred_tallies_match_oracle(orc, case):
-    """Tally sweeps are folded into the histogram in bursts; the mode read between calls,
-    after a state reset or at any sweep count must still count every tally sweep once."""
+    """Tally strides of 1 to 5 and sweep counts split over several calls: the mode read
+    between calls, after a state reset or at any sweep count counts every tally sweep
+    once, as the CPU reference does."""
     torch = torch_cuda()
     L, C, stride, calls, reset_after = case
     H, W = 21, 34
@@ -315,10 +316,18 @@ def test_sweep_index_stops_at_32_bits():
     g.close()
 
 
-def test_full_size_c3_sampled_sites(orc):
-    """2048x2048, L = 256, 16 chains in the benchmark's launch configuration: one sweep from
-    the oracle's initial state and one from an oracle-made random state at sweep 777,
-    checked at 3000 sampled (chain, pixel) sites each, plus the mean accumulator."""
+def _host_threads():
+    import os
+    return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def test_full_size_c3_whole_lattice(orc):
+    """2048x2048, L = 256, 16 chains in the benchmark's launch configuration.  Sweep 0 from
+    the oracle's initial state, checked at 3000 sampled (chain, pixel) sites and the
+    lattice corners; then sweep 777 from an oracle-made random state, checked at every one
+    of the 2048 x 2048 x 16 site updates against the oracle (computed in row bands on the
+    host's cores).  The accumulators hold exactly the two new states: the uint32 level sum
+    at every pixel, and the uint16 tallies on the first and last 64 rows."""
     torch = torch_cuda()
     wl = synth.make_workload("c3")
     kw = wl.params(burn_in=0)
@@ -328,21 +337,56 @@ def test_full_size_c3_sampled_sites(orc):
     assert np.array_equal(gpu.state().cpu().numpy(), x0)
     rng = np.random.default_rng(31)
     N = wl.height * wl.width
-    for t, start in ((0, x0), (777, None)):
-        if start is None:
-            start = rng.integers(0, 256, size=x0.shape, dtype=np.uint8)
-            gpu.set_state(torch.from_numpy(start).cuda(), t)
-        gpu.sweep(1)
-        got = gpu.state().cpu().numpy()
-        chains = rng.integers(0, 16, size=3000).astype(np.int32)
-        pix = rng.integers(0, N, size=3000).astype(np.int64)
-        # include the lattice corners and edges
-        pix[:4] = [0, wl.width - 1, N - wl.width, N - 1]
-        want = orc.update_sites(p, wl.obs, start, t, chains, pix)
-        assert np.array_equal(got.reshape(16, -1)[chains, pix], want)
-    # the mean accumulator holds exactly the sum of the two accumulated states
-    _, count, _ = gpu.stats()
-    assert count == 32
+    gpu.sweep(1)
+    new0 = gpu.state().cpu().numpy()
+    chains = rng.integers(0, 16, size=3000).astype(np.int32)
+    pix = rng.integers(0, N, size=3000).astype(np.int64)
+    pix[:4] = [0, wl.width - 1, N - wl.width, N - 1]
+    want = orc.update_sites(p, wl.obs, x0, 0, chains, pix)
+    assert np.array_equal(new0.reshape(16, -1)[chains, pix], want)
+
+    start = rng.integers(0, 256, size=x0.shape, dtype=np.uint8)
+    gpu.set_state(torch.from_numpy(start).cuda(), 777)
+    gpu.sweep(1)
+    new1 = gpu.state().cpu().numpy()
+    want1 = orc.pca_sweep_threaded(p, wl.obs, start, 777, threads=_host_threads())
+    bad = int((new1 != want1).sum())
+    assert bad == 0, f"{bad} of {new1.size} site updates differ"
+
+    assert gpu.stats() == (778, 32, 2)
+    s, h = gpu.accumulators()
+    want_sum = new0.sum(axis=0, dtype=np.uint32) + new1.sum(axis=0, dtype=np.uint32)
+    assert np.array_equal(s.cpu().numpy().view(np.uint32), want_sum)
+    for rows in (slice(0, 64), slice(wl.height - 64, wl.height)):
+        got_h = h[rows].cpu().numpy().view(np.uint16)
+        both = np.concatenate([new0[:, rows], new1[:, rows]], axis=0).reshape(32, -1)
+        cell = np.arange(both.shape[1], dtype=np.int64)[None, :] * 256 + both
+        want_h = np.bincount(cell.reshape(-1), minlength=both.shape[1] * 256).reshape(got_h.shape)
+        assert np.array_equal(got_h, want_h.astype(np.uint16))
+    gpu.close()
+
+
+def test_set_state_rejects_values_outside_the_levels():
+    """A state value >= levels is refused (PCA_EINVAL) and leaves the context as it was;
+    levels - 1 is accepted."""
+    torch = torch_cuda()
+    from paper_2507_14869_amd import PCA_EINVAL, PcaError
+    wl = synth.make_workload("c2", height=24, width=20, chains=5)
+    g = gpu_sampler(wl.obs, **wl.params(burn_in=0))
+    g.sweep(2)
+    before = g.state().cpu().numpy()
+    bad = before.copy()
+    bad[4, 23, 19] = 16  # one value past the last level, in the last chain's last pixel
+    with pytest.raises(PcaError) as e:
+        g.set_state(torch.from_numpy(bad).cuda(), 9)
+    assert e.value.code == PCA_EINVAL
+    assert g.stats()[0] == 2
+    assert np.array_equal(g.state().cpu().numpy(), before)
+    top = np.full_like(before, 15)
+    g.set_state(torch.from_numpy(top).cuda(), 9)
+    assert g.stats()[0] == 9
+    assert np.array_equal(g.state().cpu().numpy(), top)
+    g.close()
 
 
 @pytest.mark.parametrize("name", ["c2", "c3"])

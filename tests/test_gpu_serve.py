@@ -100,6 +100,7 @@ def test_memory_budget_queues_requests_and_keeps_results(orc):
     ref = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(specs[2][5])
     mean, mpm, state = sv.result(ids[2])
     assert np.array_equal(mean, ref.posterior_mean()) and np.array_equal(state, ref.state)
+    assert np.array_equal(mpm, ref.marginal_map())
     sv.release(ids[0])
     with pytest.raises(Exception):
         sv.status(ids[0])
@@ -175,4 +176,94 @@ def test_requests_with_different_kernels_share_the_server():
         ref = _alone(obs, kw, 9)
         assert np.array_equal(state, ref[2]), rid
         assert np.array_equal(mean, ref[0]) and np.array_equal(mpm, ref[1]), rid
+    sv.close()
+
+
+def _drain(sv, ids, limit=400):
+    done = []
+    for _ in range(limit):
+        sv.step()
+        done += sv.completed()
+        if set(done) >= set(ids):
+            break
+    return done
+
+
+def test_failed_admission_waits_then_fails_without_stalling_the_queue(monkeypatch):
+    """A request whose device allocation fails at admission (forced from the host with
+    PCA_FAULT_INJECT) waits while another request holds device memory, then fails with
+    PCA_ENOMEM once nothing else is admitted; the requests around it finish with results
+    equal to each run alone."""
+    from paper_2507_14869_amd import PCA_ENOMEM, PcaError
+    sv = _server(budget=1 << 34, k=4, step_ms=0.05)
+    probs = [_problem(40, 30, 16, 2, 51), _problem(30, 30, 256, 2, 52), _problem(25, 44, 2, 2, 53)]
+    ids = [sv.submit(obs, 9, **kw) for obs, kw in probs]
+    monkeypatch.setenv("PCA_FAULT_INJECT", f"admit:{ids[1]}")
+    sv.step()
+    assert sv.status(ids[1])[0] == 0  # the first request holds memory: the failed one waits
+    assert sv.status(ids[0])[0] in (1, 2)
+    done = _drain(sv, ids)
+    assert sorted(done) == sorted(ids)
+    assert sv.status(ids[1]) == (3, 0)
+    with pytest.raises(PcaError) as err:
+        sv.result(ids[1])
+    assert err.value.code == PCA_ENOMEM
+    for rid, (obs, kw) in ((ids[0], probs[0]), (ids[2], probs[2])):
+        mean, mpm, state = sv.result(rid)
+        ref = _alone(obs, kw, 9)
+        assert np.array_equal(mean, ref[0]) and np.array_equal(mpm, ref[1]) and np.array_equal(state, ref[2])
+    assert sv.stats()[:3] == (0, 0, 0)
+    sv.release(ids[1])
+    sv.close()
+
+
+def test_request_larger_than_device_memory_fails_and_the_next_one_runs():
+    """The budget is the caller's estimate: a request whose chain states exceed the
+    device's whole memory passes the budget but its allocation fails; with nothing else
+    admitted it fails with PCA_ENOMEM, and the small request queued behind it completes
+    with the result it has alone."""
+    torch = torch_cuda()
+    from paper_2507_14869_amd import PCA_ENOMEM, PcaError
+    total = torch.cuda.get_device_properties(0).total_memory
+    chains = 1024
+    side = int(np.ceil(np.sqrt(1.1 * total / (2 * chains))))  # two state buffers of side^2 x 1024 bytes
+    sv = _server(budget=1 << 50, k=4, step_ms=0.05)
+    big = np.zeros((side, side), dtype=np.float32)
+    big_id = sv.submit(big, 1, levels=2, chains=chains, prior=0, J=0.8, q=1.0, sigma=0.5, vmin=0.0, vmax=1.0,
+                       seed=1, burn_in=0, tally_stride=0)
+    del big
+    obs, kw = _problem(33, 27, 16, 2, 54)
+    small_id = sv.submit(obs, 6, **kw)
+    done = _drain(sv, [big_id, small_id])
+    assert sorted(done) == sorted([big_id, small_id])
+    assert sv.status(big_id)[0] == 3
+    with pytest.raises(PcaError) as err:
+        sv.result(big_id)
+    assert err.value.code == PCA_ENOMEM
+    mean, mpm, state = sv.result(small_id)
+    ref = _alone(obs, kw, 6)
+    assert np.array_equal(mean, ref[0]) and np.array_equal(mpm, ref[1]) and np.array_equal(state, ref[2])
+    assert sv.stats()[:3] == (0, 0, 0)
+    sv.close()
+
+
+def test_failed_read_out_ends_the_request_without_an_extra_sweep(monkeypatch):
+    """A request whose results cannot be copied out (host allocation forced to fail) ends
+    as failed after exactly its sweeps, releases its device memory, and the other
+    requests' results are unchanged."""
+    from paper_2507_14869_amd import PCA_ENOMEM, PcaError
+    sv = _server(budget=1 << 34, k=3, step_ms=0.05)
+    probs = [_problem(36, 28, 33, 2, 55), _problem(20, 50, 16, 2, 56)]
+    ids = [sv.submit(obs, 7, **kw) for obs, kw in probs]
+    monkeypatch.setenv("PCA_FAULT_INJECT", f"readout:{ids[0]}")
+    done = _drain(sv, ids)
+    assert sorted(done) == sorted(ids)
+    assert sv.status(ids[0]) == (3, 7)
+    with pytest.raises(PcaError) as err:
+        sv.result(ids[0])
+    assert err.value.code == PCA_ENOMEM
+    mean, mpm, state = sv.result(ids[1])
+    ref = _alone(*probs[1], 7)
+    assert np.array_equal(mean, ref[0]) and np.array_equal(mpm, ref[1]) and np.array_equal(state, ref[2])
+    assert sv.stats()[:3] == (0, 0, 0)
     sv.close()
