@@ -10,7 +10,7 @@ from __future__ import annotations
 from typing import Optional, Sequence
 
 from . import _lib
-from ._lib import (PCA_EBUSY, PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_params, pca_destroy,  # noqa
+from ._lib import (PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE, PCA_EBUSY, PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_params, pca_destroy,  # noqa
                    pca_get_state, pca_init, pca_last_error, pca_marginal_map, pca_posterior_mean, pca_set_state, pca_stats,
                    pca_sweep, pca_sync, pca_batch_init, pca_batch_autotune, pca_batch_config, pca_batch_set_config,
                    pca_batch_sweep, pca_batch_posterior_mean, pca_batch_marginal_map, pca_batch_get_state,
