@@ -35,6 +35,17 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(out: str) -> str:
+    """Compile ``orc.c`` with AddressSanitizer and UndefinedBehaviorSanitizer (any report
+    aborts) into ``out``; load it by setting ORC_LIB to that path in a process started with
+    the ASan runtime preloaded."""
+    cmd = ["gcc", "-O1", "-g", "-std=c99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+           "-o", out, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
+
+
 class _Params(ctypes.Structure):
     _fields_ = [
         ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("levels", ctypes.c_int32),
@@ -82,9 +93,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build()
-        L = ctypes.CDLL(_LIB)
+        path = os.environ.get("ORC_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(path):
+                build()
+        L = ctypes.CDLL(path)
         P = ctypes.POINTER
         u8, u16, u32, f32 = P(ctypes.c_uint8), P(ctypes.c_uint16), P(ctypes.c_uint32), P(ctypes.c_float)
         i32, i64 = P(ctypes.c_int32), P(ctypes.c_int64)
