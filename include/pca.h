@@ -274,6 +274,36 @@ int pca_server_stats(const pca_server *sv, int32_t *queued, int32_t *active, uin
 /* Waits for the last stream used and frees everything.  NULL is a no-op. */
 int pca_server_destroy(pca_server *sv);
 
+/* ------------------------------------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  pca_run_static allocates nothing: it
+ * runs a whole job - pca_init, pca_sweep(sweeps), then the read-outs - with the chain
+ * states, the observation in level units and the accumulators in a fixed device array of
+ * PCA_STATIC_SCRATCH_BYTES that the library holds on each device it runs on until the
+ * process ends.  The results are bit-identical to that sequence of calls with the same
+ * parameters.  Every call on a device shares that device's array (it keeps the last
+ * call's contents; the accumulators are cleared by a kernel at the start of each call), so
+ * calls that overlap on one device - on different streams or from different threads -
+ * race and give undefined results.
+ * ------------------------------------------------------------------------------------ */
+#define PCA_STATIC_SCRATCH_BYTES ((uint64_t)256 << 20)
+
+/* Enqueues the job on `stream` and returns (nothing is waited for).
+ * params, obs_dev: as for pca_init (params->beta, if any, is read during this call only).
+ * sweeps >= 0: sweeps to run from sweep index 0.
+ * mean_out_dev: device float32 [height][width] for the posterior mean, or NULL.
+ * mpm_out_dev: device uint8 [height][width] for the marginal mode, or NULL.
+ * state_out_dev: device uint8 [chains][height][width] for the last states, or NULL.
+ * Working memory, in bytes, each part rounded up to 256: 4*N (observation) + 2*N*Cp
+ * (states; Cp = chains, or chains rounded up to a multiple of 4 when chains >= 3) + 4*N
+ * (level sum) + 4*N*ceil(levels/2) when tally_stride > 0 (histogram), N = height*width.
+ * Errors: PCA_EINVAL (bad parameters or pointers, no output requested, or working memory
+ * above PCA_STATIC_SCRATCH_BYTES), PCA_ESTATE (a requested output that the run does not
+ * produce: mean with no accumulated sweep, mode with the histogram disabled or never
+ * tallied; or an accumulator that could overflow), PCA_EDEVICE. */
+int pca_run_static(const pca_params *params, const float *obs_dev, int32_t sweeps, float *mean_out_dev,
+                   uint8_t *mpm_out_dev, uint8_t *state_out_dev, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ from ._lib import (PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE, PCA_
                    pca_batch_stats, pca_batch_sync, pca_batch_destroy, pca_server_create, pca_server_submit,
                    pca_server_step, pca_server_completed, pca_server_status, pca_server_result, pca_server_release,
                    pca_server_stats, pca_server_set_shedding, pca_server_shed_count, pca_server_destroy,
-                   pca_get_accumulators, pca_set_accumulators)
+                   pca_get_accumulators, pca_set_accumulators, pca_run_static)
 
 
 def _stream_handle(stream) -> int:

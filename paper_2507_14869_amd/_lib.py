@@ -22,7 +22,7 @@ EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "
             "pca_batch_get_state", "pca_batch_stats", "pca_batch_sync", "pca_batch_destroy", "pca_server_create",
             "pca_server_submit", "pca_server_step", "pca_server_completed", "pca_server_status", "pca_server_result",
             "pca_server_release", "pca_server_stats", "pca_server_set_shedding", "pca_server_shed_count",
-            "pca_server_destroy", "pca_last_error")
+            "pca_server_destroy", "pca_run_static", "pca_last_error")
 
 
 class PcaError(RuntimeError):
@@ -95,6 +95,7 @@ def load():
         lib.pca_server_set_shedding.argtypes = [vp, ctypes.c_double]
         lib.pca_server_shed_count.argtypes = [vp, i64p]
         lib.pca_server_destroy.argtypes = [vp]
+        lib.pca_run_static.argtypes = [pp, vp, ctypes.c_int32, vp, vp, vp, vp]
         lib.pca_last_error.argtypes = []
         lib.pca_last_error.restype = ctypes.c_char_p
         for name in EXPORTED[:-1]:
@@ -313,3 +314,10 @@ def pca_server_stats(sv: int):
 
 def pca_server_destroy(sv: int):
     _check(load().pca_server_destroy(ctypes.c_void_p(sv)), "pca_server_destroy")
+
+
+def pca_run_static(params: pca_params, obs_ptr: int, sweeps: int, mean_ptr: int = 0, mpm_ptr: int = 0,
+                   state_ptr: int = 0, stream: int = 0):
+    _check(load().pca_run_static(ctypes.byref(params), ctypes.c_void_p(obs_ptr), int(sweeps),
+                                 ctypes.c_void_p(mean_ptr or None), ctypes.c_void_p(mpm_ptr or None),
+                                 ctypes.c_void_p(state_ptr or None), ctypes.c_void_p(stream)), "pca_run_static")

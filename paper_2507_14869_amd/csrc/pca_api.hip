@@ -10,7 +10,6 @@
 #include <cstdlib>
 #include <cstring>
 #include <new>
-#include <string>
 #include <vector>
 
 #include "pca.h"
@@ -34,16 +33,16 @@ struct pca_ctx {
 
 namespace {
 
-thread_local std::string g_err;
+// The calling thread's last error message: a fixed buffer, so that reporting an error
+// allocates nothing.
+thread_local char g_err[512];
 
 int fail(int code, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -80,13 +79,6 @@ int validate(const pca_params *p)
     return PCA_OK;
 }
 
-double beta_at(const pca_ctx *ctx, int64_t t)
-{
-    if (ctx->beta.empty()) return 1.0;
-    if (t >= (int64_t)ctx->beta.size()) return (double)ctx->beta.back();
-    return (double)ctx->beta[(size_t)t];
-}
-
 double level_scale(const pca_params &p) { return (double)(p.levels - 1) / ((double)p.vmax - (double)p.vmin); }
 
 void release(pca_ctx *ctx)
@@ -100,6 +92,73 @@ void release(pca_ctx *ctx)
     delete ctx;
 }
 
+pcak::RunBuffers run_buffers(const pca_ctx *ctx)
+{
+    pcak::RunBuffers b{};
+    b.gp = ctx->gp;
+    b.x[0] = ctx->x[0];
+    b.x[1] = ctx->x[1];
+    b.sum = ctx->sum;
+    b.hist = ctx->hist;
+    b.G = ctx->G;
+    b.Cp = ctx->Cp;
+    b.T = ctx->T;
+    b.hist_words = ctx->hist_words;
+    return b;
+}
+
+}  // namespace
+
+pcak::RunBuffers pcak::run_layout(const pca_params &p)
+{
+    RunBuffers b{};
+    b.G = chain_group(p.chains);
+    b.Cp = (p.chains + b.G - 1) / b.G * b.G;
+    b.T = p.prior == PCA_PRIOR_POTTS ? 1 : (p.trunc < p.levels - 1 ? p.trunc : p.levels - 1);
+    b.hist_words = (p.levels + 1) / 2;
+    return b;
+}
+
+hipError_t pcak::enqueue_sweeps(const pca_params &p, const float *beta, int beta_len, const RunBuffers &b, int64_t t0,
+                                int32_t n, int &cur, int32_t *done, hipStream_t s)
+{
+    SweepArgs a{};
+    a.gp = b.gp;
+    a.H = p.height;
+    a.W = p.width;
+    a.L = p.levels;
+    a.C = p.chains;
+    a.Cp = b.Cp;
+    a.T = b.T;
+    a.hist_words = b.hist_words;
+    a.J = (double)p.J;
+    a.q = (double)p.q;
+    a.kappa = p.prior == PCA_PRIOR_POTTS ? 2.0 : 1.0;
+    a.inertia = p.inertia;
+    a.sigma_s = (double)p.sigma * level_scale(p);
+    a.key0 = (uint32_t)p.seed;
+    a.key1 = (uint32_t)(p.seed >> 32);
+    *done = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t t = t0 + i;
+        const bool acc = t >= p.burn_in;
+        const bool tally = acc && p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0;
+        a.xin = b.x[cur];
+        a.xout = b.x[cur ^ 1];
+        a.sum = acc ? b.sum : nullptr;
+        a.hist = tally ? b.hist : nullptr;
+        a.beta = beta_len == 0 ? 1.0 : (double)beta[t < beta_len ? t : beta_len - 1];
+        a.t = (uint32_t)t;
+        const hipError_t e = launch_sweep(a, b.G, p.neighbourhood, s);
+        if (e != hipSuccess) return e;
+        cur ^= 1;
+        *done = i + 1;
+    }
+    return hipSuccess;
+}
+
+namespace {
+
 int check_ctx(const pca_ctx *ctx)
 {
     if (!ctx) return fail(PCA_EINVAL, "ctx is NULL");
@@ -112,7 +171,7 @@ int pcak::validate_params(const pca_params *p) { return validate(p); }
 
 int pcak::set_error(int code, const char *message)
 {
-    g_err = message;
+    if (message != g_err) snprintf(g_err, sizeof g_err, "%s", message);
     return code;
 }
 
@@ -140,11 +199,11 @@ bool pcak::fault_injected(const char *site, int64_t id)
 
 extern "C" {
 
-const char *pca_last_error(void) { return g_err.c_str(); }
+const char *pca_last_error(void) { return g_err; }
 
 int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_ctx **out)
 {
-    g_err.clear();
+    g_err[0] = 0;
     if (!out) return fail(PCA_EINVAL, "out is NULL");
     *out = nullptr;
     int rc = validate(params);
@@ -162,12 +221,12 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
         return fail(PCA_ENOMEM, "host allocation failed");
     }
     ctx->p.beta = nullptr;
-    ctx->G = pcak::chain_group(params->chains);
-    ctx->Cp = (params->chains + ctx->G - 1) / ctx->G * ctx->G;
-    ctx->T = params->prior == PCA_PRIOR_POTTS ? 1 : (params->trunc < params->levels - 1 ? params->trunc
-                                                                                         : params->levels - 1);
+    const pcak::RunBuffers lay = pcak::run_layout(*params);
+    ctx->G = lay.G;
+    ctx->Cp = lay.Cp;
+    ctx->T = lay.T;
+    ctx->hist_words = lay.hist_words;
     ctx->N = (int64_t)params->height * params->width;
-    ctx->hist_words = (params->levels + 1) / 2;
     ctx->last = s;
 
     const size_t N = (size_t)ctx->N;
@@ -210,7 +269,7 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
 
 int pca_sweep(pca_ctx *ctx, int32_t n, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (n < 0) return fail(PCA_EINVAL, "n must be >= 0");
@@ -229,45 +288,21 @@ int pca_sweep(pca_ctx *ctx, int32_t n, void *stream)
 
     hipStream_t s = (hipStream_t)stream;
     ctx->last = s;
-    pcak::SweepArgs a{};
-    a.gp = ctx->gp;
-    a.H = p.height;
-    a.W = p.width;
-    a.L = p.levels;
-    a.C = p.chains;
-    a.Cp = ctx->Cp;
-    a.T = ctx->T;
-    a.hist_words = ctx->hist_words;
-    a.J = (double)p.J;
-    a.q = (double)p.q;
-    a.kappa = p.prior == PCA_PRIOR_POTTS ? 2.0 : 1.0;
-    a.inertia = p.inertia;
-    a.sigma_s = (double)p.sigma * level_scale(p);
-    a.key0 = (uint32_t)p.seed;
-    a.key1 = (uint32_t)(p.seed >> 32);
-    for (int32_t i = 0; i < n; ++i) {
-        const int64_t t = ctx->t;
-        const bool acc = t >= p.burn_in;
-        const bool tally = acc && p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0;
-        a.xin = ctx->x[ctx->cur];
-        a.xout = ctx->x[ctx->cur ^ 1];
-        a.sum = acc ? ctx->sum : nullptr;
-        a.hist = tally ? ctx->hist : nullptr;
-        a.beta = beta_at(ctx, t);
-        a.t = (uint32_t)t;
-        hipError_t e = pcak::launch_sweep(a, ctx->G, p.neighbourhood, s);
-        if (e != hipSuccess) return hip_fail(e, "pca_sweep");
-        ctx->cur ^= 1;
-        ctx->t += 1;
-        if (acc) ctx->count += p.chains;
-        if (tally) ctx->tallies += 1;
-    }
-    return PCA_OK;
+    const pcak::RunBuffers b = run_buffers(ctx);
+    int32_t done = 0;
+    const hipError_t e = pcak::enqueue_sweeps(p, ctx->beta.empty() ? nullptr : ctx->beta.data(), (int)ctx->beta.size(),
+                                              b, ctx->t, n, ctx->cur, &done, s);
+    // the sweeps enqueued before a failed launch still count
+    pcak::accumulating_sweeps(ctx->t, done, p.burn_in, p.tally_stride, &add_sweeps, &add_tallies);
+    ctx->t += done;
+    ctx->count += add_sweeps * p.chains;
+    ctx->tallies += add_tallies;
+    return e == hipSuccess ? PCA_OK : hip_fail(e, "pca_sweep");
 }
 
 int pca_posterior_mean(pca_ctx *ctx, float *out_dev, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out_dev) return fail(PCA_EINVAL, "out_dev is NULL");
@@ -282,7 +317,7 @@ int pca_posterior_mean(pca_ctx *ctx, float *out_dev, void *stream)
 
 int pca_marginal_map(pca_ctx *ctx, uint8_t *out_dev, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out_dev) return fail(PCA_EINVAL, "out_dev is NULL");
@@ -296,7 +331,7 @@ int pca_marginal_map(pca_ctx *ctx, uint8_t *out_dev, void *stream)
 
 int pca_get_state(pca_ctx *ctx, uint8_t *out_dev, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!out_dev) return fail(PCA_EINVAL, "out_dev is NULL");
@@ -308,7 +343,7 @@ int pca_get_state(pca_ctx *ctx, uint8_t *out_dev, void *stream)
 
 int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!in_dev) return fail(PCA_EINVAL, "in_dev is NULL");
@@ -331,7 +366,7 @@ int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream)
 
 int pca_get_accumulators(pca_ctx *ctx, uint32_t *sum_dev, uint16_t *hist_dev, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!sum_dev) return fail(PCA_EINVAL, "sum_dev is NULL");
@@ -352,7 +387,7 @@ int pca_get_accumulators(pca_ctx *ctx, uint32_t *sum_dev, uint16_t *hist_dev, vo
 int pca_set_accumulators(pca_ctx *ctx, const uint32_t *sum_dev, const uint16_t *hist_dev, int64_t count,
                          int64_t tallies, void *stream)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     if (!sum_dev) return fail(PCA_EINVAL, "sum_dev is NULL");
@@ -387,7 +422,7 @@ int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *talli
 
 int pca_sync(pca_ctx *ctx)
 {
-    g_err.clear();
+    g_err[0] = 0;
     int rc = check_ctx(ctx);
     if (rc) return rc;
     hipError_t e = hipStreamSynchronize(ctx->last);
@@ -397,7 +432,7 @@ int pca_sync(pca_ctx *ctx)
 
 int pca_destroy(pca_ctx *ctx)
 {
-    g_err.clear();
+    g_err[0] = 0;
     if (!ctx) return PCA_OK;
     hipError_t e = hipStreamSynchronize(ctx->last);
     release(ctx);

@@ -138,6 +138,25 @@ hipError_t launch_advance(ImageDesc *imgs, int n_imgs, uint32_t n, hipStream_t s
 hipError_t launch_sweep_inertia(const SweepArgs &a, int G, int nbr, hipStream_t s);
 hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int blocks, int G, int tiled, int nbr, hipStream_t s);
 
+// Device buffers of one single-lattice run and the chain layout that goes with them.
+struct RunBuffers {
+    float *gp;           // [N] observation in level units
+    uint8_t *x[2];       // [N][Cp] double-buffered chain states
+    uint32_t *sum;       // [N] level sums
+    uint32_t *hist;      // [N][hist_words] packed uint16 counters, or nullptr (no histogram)
+    int G, Cp, T, hist_words;
+};
+
+// Chain grouping, truncation and histogram row length of a run (buffers left null).
+RunBuffers run_layout(const pca_params &p);
+
+// Enqueues sweeps t0 .. t0+n-1 of a run on `b`: sweep t reads b.x[cur] and writes the other
+// buffer, and cur flips once per sweep enqueued.  beta: host array of beta_len per-sweep
+// values (none: beta = 1).  Returns the first launch error; *done receives the number of
+// sweeps enqueued before it (n on success).
+hipError_t enqueue_sweeps(const pca_params &p, const float *beta, int beta_len, const RunBuffers &b, int64_t t0,
+                          int32_t n, int &cur, int32_t *done, hipStream_t s);
+
 // Shared by the single-lattice and batch entry points (pca_api.hip).
 int validate_params(const pca_params *p);     // PCA_OK or PCA_EINVAL with the error message set
 int set_error(int code, const char *message);  // records the calling thread's last error, returns code

@@ -109,3 +109,36 @@ def test_injected_allocation_failure_in_init(lib, monkeypatch):
     with pytest.raises(_lib.PcaError) as e:
         _lib.pca_init(bad, 0x1000)
     assert e.value.code == _lib.PCA_EINVAL
+
+
+@pytest.mark.parametrize("case", ["bad_params", "null_obs", "negative_sweeps", "no_output", "mode_without_histogram",
+                                  "mean_without_accumulation", "too_large"])
+def test_run_static_rejects_bad_calls_without_a_device(lib, case):
+    """pca_run_static checks its arguments and the size of its working memory on the host,
+    before it looks up the device array: every refusal here happens without a GPU."""
+    from paper_2507_14869_amd import _lib
+    kw = dict(height=8, width=8, levels=16, chains=4, J=0.1, q=0.5, sigma=1.0, tally_stride=1)
+    obs, sweeps, mean, mpm, want = 0x1000, 3, 0x2000, 0x3000, _lib.PCA_EINVAL
+    if case == "bad_params":
+        kw["levels"] = 1
+    elif case == "null_obs":
+        obs = 0
+    elif case == "negative_sweeps":
+        sweeps = -1
+    elif case == "no_output":
+        mean = mpm = 0
+    elif case == "mode_without_histogram":
+        kw["tally_stride"] = 0
+        want = _lib.PCA_ESTATE
+    elif case == "mean_without_accumulation":
+        kw["burn_in"] = 5
+        want = _lib.PCA_ESTATE
+    elif case == "too_large":
+        # 2048 x 2048, 16 chains, 256 levels with a histogram: about 2.3 GB of working memory
+        kw.update(height=2048, width=2048, chains=16, levels=256)
+    p, _buf = _lib.make_params(**kw)
+    with pytest.raises(_lib.PcaError) as e:
+        _lib.pca_run_static(p, obs, sweeps, mean, mpm)
+    assert e.value.code == want
+    if case == "too_large":
+        assert "working memory" in _lib.pca_last_error()
