@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpca.so")
 SOURCES = ["pca_kernels.hip", "pca_kernels_batch.hip", "pca_kernels_inertia.hip", "pca_api.hip", "pca_batch.hip",
-           "pca_serve.hip", "pca_static.hip"]
+           "pca_serve.hip", "pca_static.hip", "pca_kernels_tb.hip"]
 BUILD_DIR = os.path.join(HERE, "_build")
 
 

@@ -4,6 +4,7 @@
 // per-site arithmetic in pca_sweep.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -139,6 +140,42 @@ hipError_t pcak::enqueue_sweeps(const pca_params &p, const float *beta, int beta
     a.key0 = (uint32_t)p.seed;
     a.key1 = (uint32_t)(p.seed >> 32);
     *done = 0;
+    const TbPlan pl = tb_plan(p.height, p.width, p.levels, b.Cp, p.neighbourhood, b.T, p.inertia);
+    if (pl.S > 0) {
+        // several sweeps per launch from LDS tiles (lattices with few levels)
+        TbArgs tb{};
+        tb.a = a;
+        tb.nbr = p.neighbourhood;
+        tb.TH = pl.TH;
+        tb.TW = pl.TW;
+        tb.tiles_w = pl.tiles_w;
+        tb.tiles = pl.tiles;
+        tb.ptab_n = p.neighbourhood * b.T + 1;
+        for (int32_t i = 0; i < n;) {
+            const int S = (int)std::min<int64_t>(pl.S, n - i);
+            tb.S = S;
+            tb.acc_mask = tb.tally_mask = 0u;
+            for (int j = 0; j < S; ++j) {
+                const int64_t t = t0 + i + j;
+                const bool acc = t >= p.burn_in;
+                const bool tally = acc && p.tally_stride > 0 && (t - p.burn_in) % p.tally_stride == 0;
+                tb.acc_mask |= (uint32_t)acc << j;
+                tb.tally_mask |= (uint32_t)tally << j;
+                tb.beta[j] = beta_len == 0 ? 1.0 : (double)beta[t < beta_len ? t : beta_len - 1];
+            }
+            tb.a.t = (uint32_t)(t0 + i);
+            tb.a.xin = b.x[cur];
+            tb.a.xout = b.x[cur ^ 1];
+            tb.a.sum = tb.acc_mask ? b.sum : nullptr;
+            tb.a.hist = tb.tally_mask ? b.hist : nullptr;
+            const hipError_t e = launch_tb_sweeps(tb, s);
+            if (e != hipSuccess) return e;
+            cur ^= 1;
+            i += S;
+            *done = i;
+        }
+        return hipSuccess;
+    }
     for (int32_t i = 0; i < n; ++i) {
         const int64_t t = t0 + i;
         const bool acc = t >= p.burn_in;

@@ -110,11 +110,10 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
         if (c.tiled) {
             const int th = pcak::kBlock / d.tpp / pcak::kTileW;
             d.tiles_w = (d.W + pcak::kTileW - 1) / pcak::kTileW;
+            d.patch = -1;
             blocks = d.tiles_w * ((d.H + th - 1) / th);
         } else {
-            d.tiles_w = 0;
-            const int64_t threads = (int64_t)d.H * d.W * d.tpp;
-            blocks = (int)((threads + pcak::kBlock - 1) / pcak::kBlock);
+            blocks = (int)pcak::untiled_layout(d);
         }
         if ((int64_t)base + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "batch grid exceeds 2^31 - 1 workgroups");
         try {

@@ -114,7 +114,8 @@ struct ImageDesc {
     uint32_t key0, key1;
     int tpp;              // threads per pixel (Cp / G) in the launch configuration in use
     int block_base;       // first workgroup of this lattice in the batched grid
-    int tiles_w;          // tiled traversal: tiles per tile row
+    int tiles_w;          // tiled traversal: tiles per tile row; patch traversal: tiles per row
+    int patch;            // untiled traversal: log2(tpp) if the pixels form 2-D patches, else -1
     uint32_t t;           // sweep index before the current replay; advanced on the device
     uint32_t t_end;       // the lattice stops advancing at this sweep index
 };
@@ -128,6 +129,17 @@ struct BatchLaunch {
 
 constexpr int kTileW = 16;  // tiled traversal: tiles 16 pixels wide, kBlock / tpp pixels each
 
+// Traversal of one lattice in an untiled batched launch, as in the single-lattice sweep:
+// 2-D pixel patches for L > 16 (when tpp allows), row-major otherwise.  Sets d.patch and
+// d.tiles_w from d.H, d.W, d.L and d.tpp; returns the lattice's workgroups.
+inline int64_t untiled_layout(ImageDesc &d)
+{
+    const SweepLayout l = sweep_layout(d.H, d.W, d.tpp, d.L > 16);
+    d.patch = l.patch;
+    d.tiles_w = l.tiles_w;
+    return l.blocks;
+}
+
 // inr: the lattices use the L1/L2 inertia form (share is then ignored).  Grids of more
 // than kMaxLaunchBlocks workgroups are issued as several launches (BatchLaunch.block0).
 hipError_t launch_batch_sweep(const BatchLaunch &b, int total_blocks, int G, int share, int tiled, int nbr, bool inr,
@@ -137,6 +149,36 @@ hipError_t launch_advance(ImageDesc *imgs, int n_imgs, uint32_t n, hipStream_t s
 // to these when the sweep (or every lattice of the batch) has inertia 1 or 2.
 hipError_t launch_sweep_inertia(const SweepArgs &a, int G, int nbr, hipStream_t s);
 hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int blocks, int G, int tiled, int nbr, hipStream_t s);
+
+// Several sweeps in one launch for lattices with L <= 16 (pca_kernels_tb.hip): each
+// workgroup advances one tile of the lattice S sweeps from an LDS copy of the tile and a
+// halo S sites deep.
+constexpr int kTbMaxSweeps = 16;
+constexpr int kTbBlock = 256;          // threads per workgroup
+constexpr int kTbMaxLds = 64 * 1024;  // LDS bytes a workgroup may use
+constexpr int64_t kTbMaxThreads = 256 * 4 * 64;  // single-sweep threads below which it is used
+
+struct TbArgs {
+    SweepArgs a;      // a.t: first sweep; a.xin: state at a.t; a.xout: receives the state at
+                      // a.t + S; a.sum / a.hist: accumulators of the sweeps the masks select
+    int S;            // sweeps of this launch, 1..kTbMaxSweeps
+    int nbr;          // neighbourhood, 4 or 8
+    int TH, TW;       // tile shape in pixels
+    int tiles_w;      // tiles per lattice row
+    int tiles;        // tiles (workgroups) in all
+    int ptab_n;       // prior table entries, nbr * T + 1
+    uint32_t acc_mask, tally_mask;  // bit s: sweep a.t + s adds to the sum / to the histogram
+    double beta[kTbMaxSweeps];      // beta of sweep a.t + s
+};
+
+// Launch plan of the multi-sweep kernel: S == 0 when it does not apply (L > 16, inertia
+// 1 or 2, or a tile with its halo would not fit the LDS limit).
+struct TbPlan {
+    int TH, TW, S, tiles_w, tiles;
+};
+
+TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia);
+hipError_t launch_tb_sweeps(const TbArgs &b, hipStream_t s);
 
 // Device buffers of one single-lattice run and the chain layout that goes with them.
 struct RunBuffers {

@@ -499,8 +499,7 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
         pcak::ImageDesc d = r->d;
         d.tpp = d.Cp / G;
         d.block_base = (int)block_img.size();
-        d.tiles_w = 0;
-        const int64_t blocks = ((int64_t)d.H * d.W * d.tpp + pcak::kBlock - 1) / pcak::kBlock;
+        const int64_t blocks = pcak::untiled_layout(d);
         d.t = (uint32_t)r->t;
         d.t_end = (uint32_t)(r->t + k[r]);
         if ((int64_t)block_img.size() + blocks > 0x7FFFFFFF) return fail(PCA_EINVAL, "server: step grid too large");

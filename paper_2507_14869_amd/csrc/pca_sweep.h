@@ -141,6 +141,24 @@ __device__ __forceinline__ void store_group(uint8_t *p, uint32_t v)
 
 // ---------------------------------------------------------------- sweep
 
+// Byte transpose of four state words (byte ch of word j = chain ch's level at neighbour j)
+// into X[ch] = the chain's four neighbour levels (byte j = neighbour j), for the G chains.
+template <int G>
+__device__ __forceinline__ void transpose_group(uint32_t A, uint32_t B, uint32_t C, uint32_t D, uint32_t (&X)[G])
+{
+    // v_perm_b32 picks bytes of {src0:src1}: selector 0-3 = src1's bytes, 4-7 = src0's
+    const uint32_t ab01 = __builtin_amdgcn_perm(B, A, 0x05010400u);  // A0 B0 A1 B1
+    const uint32_t cd01 = __builtin_amdgcn_perm(D, C, 0x05010400u);  // C0 D0 C1 D1
+    X[0] = __builtin_amdgcn_perm(cd01, ab01, 0x05040100u);           // A0 B0 C0 D0
+    if constexpr (G >= 2) X[1] = __builtin_amdgcn_perm(cd01, ab01, 0x07060302u);  // A1 B1 C1 D1
+    if constexpr (G == 4) {
+        const uint32_t ab23 = __builtin_amdgcn_perm(B, A, 0x07030602u);  // A2 B2 A3 B3
+        const uint32_t cd23 = __builtin_amdgcn_perm(D, C, 0x07030602u);  // C2 D2 C3 D3
+        X[2] = __builtin_amdgcn_perm(cd23, ab23, 0x05040100u);
+        X[3] = __builtin_amdgcn_perm(cd23, ab23, 0x07060302u);
+    }
+}
+
 // Per-chain neighbour data for the byte-wise statistic.  With lo_j = max(x_j - T_j, 0),
 // hi_j = min(x_j + T_j, 255) and T_j = 0 for absent neighbours, for every k in [0, 255]
 //   2 min(|k - x_j|, T_j) = 2|k - x_j| - |k - hi_j| - |k - lo_j| + (hi_j - lo_j),
@@ -245,16 +263,31 @@ struct SweepConsts {
     float R, a2, q2;
 };
 
-__device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nbr, float *ptab)
+// FP32 constants of a sweep from the run parameters and the sweep's beta (fixed operation
+// order, identical in every kernel).
+__device__ __forceinline__ SweepConsts sweep_constants(const SweepArgs &a)
 {
-    const float c2 = (float)(((a.beta * a.J) * a.kappa) * kLog2e);
     const float q2 = (float)((a.beta * a.q) * kLog2e);
     SweepConsts k;
     k.R = exp2s(q2) - 1.0f;
     k.q2 = q2;
     k.a2 = (float)(kLog2e / ((2.0 * a.sigma_s) * a.sigma_s));
+    return k;
+}
+
+// Entries s = first, first + stride, ... of the prior factor table P(S) = exp2s(-(c2 S)),
+// S = 0..nbr*T.
+__device__ __forceinline__ void fill_prior_table(const SweepArgs &a, int nbr, float *ptab, int first, int stride)
+{
+    const float c2 = (float)(((a.beta * a.J) * a.kappa) * kLog2e);
     const int nP = nbr * a.T + 1;
-    for (int s = threadIdx.x; s < nP; s += blockDim.x) ptab[s] = exp2s(-(c2 * (float)s));
+    for (int s = first; s < nP; s += stride) ptab[s] = exp2s(-(c2 * (float)s));
+}
+
+__device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nbr, float *ptab)
+{
+    const SweepConsts k = sweep_constants(a);
+    fill_prior_table(a, nbr, ptab, threadIdx.x, blockDim.x);
     __syncthreads();
     return k;
 }
@@ -286,42 +319,71 @@ __device__ __forceinline__ float inertia_fmax(float gp, int x, int L, int p, flo
     return F1 > F2 ? F1 : F2;
 }
 
-// One thread's site updates: pixel (r, c) = pix, chains grp*G .. grp*G+G-1.  `q` is the
-// thread's position in its group of SHARE lanes serving the same pixel.
+// First index b in [0, 16) with part[b][ch] > tf, given that part[.][ch] is nondecreasing
+// and part[15][ch] > tf: a branch-free binary search (halving the candidates four times).
+template <int G>
+__device__ __forceinline__ int first_above(const float (&part)[16][G], int ch, float tf)
+{
+    float v8[8], v4[4], v2[2];
+    const bool c8 = part[7][ch] > tf;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v8[i] = c8 ? part[i][ch] : part[8 + i][ch];
+    int base = c8 ? 0 : 8;
+    const bool c4 = v8[3] > tf;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v4[i] = c4 ? v8[i] : v8[4 + i];
+    base += c4 ? 0 : 4;
+    const bool c2 = v4[1] > tf;
+#pragma unroll
+    for (int i = 0; i < 2; ++i) v2[i] = c2 ? v4[i] : v4[2 + i];
+    base += c2 ? 0 : 2;
+    return base + (v2[0] > tf ? 0 : 1);
+}
+
+// What one thread's site updates read: the observation, its chain group's current levels
+// and those of each neighbour, however the caller holds the state (global memory or an
+// LDS tile).
+template <int NBR>
+struct SiteInputs {
+    float gp;            // observation in level units
+    uint32_t own;        // byte ch: level of chain grp*G + ch at this pixel
+    uint32_t nbw[NBR];   // the same for each neighbour (0 if absent)
+    bool present[NBR];   // neighbour inside the lattice
+};
+
+// Neighbour offsets (row, column); the first four are the 4-neighbourhood.
+__device__ constexpr int kNbrDr[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
+__device__ constexpr int kNbrDc[8] = {0, 0, -1, 1, -1, 1, -1, 1};
+
+// One thread's site updates: pixel `pix`, chains grp*G .. grp*G+G-1, from the inputs `in`.
+// `q` is the thread's position in its group of SHARE lanes serving the same pixel.  Returns
+// the new levels packed one per byte and also in knew.
 // INR selects the L1/L2 inertia form (a.inertia = 1 or 2; SHARE must then be 1).
 template <int G, int NBR, int SUB, int NBLK, int SHARE, bool INR = false>
-__device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab, SweepConsts kc, int pix, int r,
-                                           int c, int grp, int q)
+__device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *ptab, SweepConsts kc,
+                                              const SiteInputs<NBR> &in, int pix, int grp, int q, int (&knew)[G])
 {
     constexpr int NW = NBR / 4;
     const float R = kc.R;
     const float a2 = kc.a2;
-    const int tpp = a.Cp / G;
     const int cofs = grp * G;
     const int L = a.L;
 
     // Observation and the data-term shift.
-    const float gp = a.gp[pix];
+    const float gp = in.gp;
     float khat = __builtin_rintf(gp);
     khat = khat < 0.0f ? 0.0f : khat;
     khat = khat > (float)(L - 1) ? (float)(L - 1) : khat;
     const float e0 = gp - khat;
     const float m = a2 * (e0 * e0);
 
-    // State words of the pixel and its neighbours (G chains each).
-    const uint8_t *xin = a.xin;
-    const uint32_t own = load_group<G>(xin + (int64_t)pix * a.Cp + cofs);
+    const uint32_t own = in.own;
     uint32_t nbw[NBR];
     bool present[NBR];
-    {
-        const int dr[8] = {-1, 1, 0, 0, -1, -1, 1, 1};
-        const int dc[8] = {0, 0, -1, 1, -1, 1, -1, 1};
 #pragma unroll
-        for (int j = 0; j < NBR; ++j) {
-            const int rr = r + dr[j], cc = c + dc[j];
-            present[j] = rr >= 0 && rr < a.H && cc >= 0 && cc < a.W;
-            nbw[j] = present[j] ? load_group<G>(xin + ((int64_t)rr * a.W + cc) * a.Cp + cofs) : 0u;
-        }
+    for (int j = 0; j < NBR; ++j) {
+        nbw[j] = in.nbw[j];
+        present[j] = in.present[j];
     }
 
     const char *pt = reinterpret_cast<const char *>(ptab);
@@ -333,16 +395,47 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
     int nlo = 1 << 20, nhi = -(1 << 20), npres = 0;
 #pragma unroll
     for (int j = 0; j < NBR; ++j) npres += present[j] ? 1 : 0;
+    if constexpr (SUB == 1) {
+        // L <= 16, so every level and T are below 16: the four neighbours of a chain are
+        // handled as the bytes of one dword (the state words transposed so that each
+        // dword holds one chain's neighbours), hi = x + T needs no clamp and lo = max(x - T, 0)
+        // is a bytewise saturating subtraction.  Absent neighbours have x = lo = hi = 0.
+        uint32_t tm[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) tm[w] = 0u;
+#pragma unroll
+        for (int j = 0; j < NBR; ++j)
+            if (present[j]) tm[j / 4] |= (uint32_t)a.T << (8 * (j % 4));
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            uint32_t X[G];
+            transpose_group<G>(nbw[4 * w], nbw[4 * w + 1], nbw[4 * w + 2], nbw[4 * w + 3], X);
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) {
+                const uint32_t hi = X[ch] + tm[w];
+                const uint32_t d = (X[ch] | 0x80808080u) - tm[w];  // byte: x - T + 128, no borrows
+                const uint32_t ge = (d & 0x80808080u) >> 7;         // byte: 1 where x >= T
+                const uint32_t lo = (d ^ 0x80808080u) & (ge * 0xFFu);
+                nb[ch].x[w] = X[ch];
+                nb[ch].lo[w] = lo;
+                nb[ch].hi[w] = hi;
+                // sum_j (hi_j - lo_j) over this dword's neighbours, twice
+                nb[ch].cb = __builtin_amdgcn_sad_u8(hi, lo, w == 0 ? 0u : (uint32_t)nb[ch].cb);
+            }
+        }
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch) nb[ch].cb *= 2;
+    }
 #pragma unroll
     for (int ch = 0; ch < G; ++ch) {
         xs[ch] = (int)((own >> (8 * ch)) & 0xFFu);
         int csum = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) {
+        for (int w = 0; w < NW && SUB > 1; ++w) {
             nb[ch].x[w] = nb[ch].lo[w] = nb[ch].hi[w] = 0u;
         }
 #pragma unroll
-        for (int j = 0; j < NBR; ++j) {
+        for (int j = 0; j < NBR && SUB > 1; ++j) {
             const int xj = (int)((nbw[j] >> (8 * ch)) & 0xFFu);
             const int Tj = present[j] ? a.T : 0;
             const int lo = xj > Tj ? xj - Tj : 0;
@@ -356,7 +449,7 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
             nb[ch].lo[j / 4] |= (uint32_t)lo << (8 * (j % 4));
             nb[ch].hi[j / 4] |= (uint32_t)hi << (8 * (j % 4));
         }
-        nb[ch].cb = 2 * csum;
+        if constexpr (SUB > 1) nb[ch].cb = 2 * csum;
         if constexpr (INR) {
             fmx[ch] = inertia_fmax(gp, xs[ch], L, a.inertia, a2, kc.q2);
             stay[ch] = 0.0f;
@@ -423,9 +516,10 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
                         kk += 0x01010101u;
                     }
                 }
-#pragma unroll
-                for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
             }
+            // (slots past the last level keep Z, which the L <= 16 draw's search relies on)
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) part[b][ch] = acc[ch];
         }
     } else if constexpr (SUB == 1) {
 #pragma unroll
@@ -444,10 +538,16 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
                         else D = group_bcast<SHARE, (SHARE > 3 ? 3 : 0)>(Dm);
                         level_update<G, NW, false>(pt, nb, acc, D, kk);
                         kk += 0x01010101u;
-#pragma unroll
-                        for (int ch = 0; ch < G; ++ch) part[k0 + j][ch] = acc[ch];
                     }
+                    // past the last level acc stays at Z, which the draw's search relies on
+#pragma unroll
+                    for (int ch = 0; ch < G; ++ch) part[k0 + j][ch] = acc[ch];
                 }
+            } else {
+#pragma unroll
+                for (int j = 0; j < SHARE; ++j)
+#pragma unroll
+                    for (int ch = 0; ch < G; ++ch) part[k0 + j][ch] = acc[ch];
             }
         }
     } else {
@@ -507,8 +607,6 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
     const int chain0 = cofs;
     const U4 rnd = philox<SUB == 1>(U4{(uint32_t)pix, a.t, (uint32_t)(chain0 >> 2), 0u}, a.key0, a.key1);
     uint32_t packed = 0u;
-    uint32_t lsum = 0u;
-    int knew[G];
 #pragma unroll
     for (int ch = 0; ch < G; ++ch) {
         const uint32_t w = word_of(rnd, (chain0 & 3) + ch);
@@ -518,19 +616,23 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         if (Z != 0.0f) {
             const float tf = threshold_rd(u, Z);
             if (!(stay[ch] > tf)) {
-                int bsel = nblk - 1;
-                float start = 0.0f;
-#pragma unroll
-                for (int b = NBLK - 1; b >= 0; --b) {
-                    if (b < nblk && part[b][ch] > tf) {
-                        bsel = b;
-                        start = b == 0 ? stay[ch] : part[b > 0 ? b - 1 : 0][ch];
-                    }
-                }
                 if constexpr (SUB == 1) {
-                    k = bsel;
+                    // the running sums are nondecreasing and every slot past the last level
+                    // holds Z > tf: binary search for the first one above tf
+                    k = first_above(part, ch, tf);
                 } else {
+                    int bsel = nblk - 1;
+                    float start = 0.0f;
+#pragma unroll
+                    for (int b = NBLK - 1; b >= 0; --b) {
+                        if (b < nblk && part[b][ch] > tf) {
+                            bsel = b;
+                            start = b == 0 ? stay[ch] : part[b > 0 ? b - 1 : 0][ch];
+                        }
+                    }
                     // Re-run the sums of the selected block; they reproduce the main pass exactly.
+                    // (A branch-free form evaluating all 16 levels measured 2% slower per sweep
+                    // on 2048x2048, L = 256, 16 chains: more spills and no early exit.)
                     const int k0 = bsel * SUB;
                     const int kend = (L - k0) < SUB ? (L - k0) : SUB;
                     float s = start;
@@ -558,38 +660,78 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         }
         knew[ch] = k;
         packed |= (uint32_t)k << (8 * ch);
-        if (chain0 + ch < a.C) lsum += (uint32_t)k;
     }
-    store_group<G>(a.xout + (int64_t)pix * a.Cp + cofs, packed);
+    return packed;
+}
 
-    if (a.sum) {
+// Tally of one thread's new levels: the level sum of its chains into sum[0] (a pixel's
+// word), its chains' uint16 counters into the pixel's histogram row hrow (either may be
+// null).  The tpp threads of a pixel are consecutive lanes; chains >= C (padding) count
+// nothing.
+template <int G, int SUB>
+__device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hist_words, int C, int tpp, int grp,
+                                           const int (&knew)[G])
+{
+    const int chain0 = grp * G;
+    if (sum) {
+        uint32_t lsum = 0u;
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch)
+            if (chain0 + ch < C) lsum += (uint32_t)knew[ch];
         // Lanes of a pixel sit in aligned pairs or quads when tpp is 2 or 4: add their sums
         // with DPP and let the first lane update the word, instead of one atomic per lane
         // (global atomics are performed past L2, one memory write each).
         if (tpp == 1) {
-            a.sum[pix] += lsum;
+            *sum += lsum;
         } else if (tpp == 2 || tpp == 4) {
             uint32_t s = lsum + (uint32_t)__builtin_amdgcn_mov_dpp((int)lsum, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
             if (tpp == 4) s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);      // [2,3,0,1]
-            if (grp == 0) a.sum[pix] += s;
+            if (grp == 0) *sum += s;
         } else {
-            atomicAdd(a.sum + pix, lsum);
+            atomicAdd(sum, lsum);
         }
     }
-    if (a.hist) {
-        uint32_t *hrow = a.hist + (int64_t)pix * a.hist_words;
-        if (SUB == 1 && (tpp == 1 || tpp == 2 || tpp == 4)) {
-            // L <= 16: the pixel's whole counter row (at most 8 words) is built in registers,
+    if (hrow) {
+        if (SUB == 1 && C <= 15 && (tpp == 1 || tpp == 2 || tpp == 4)) {
+            // L <= 16 and at most 15 chains: a pixel's 16 counters fit one 64-bit word of
+            // 4-bit counters (no count reaches 16), built by shifts, summed across the
+            // pixel's lanes with DPP and widened to the uint16 row, each lane adding its
+            // words with plain read-modify-writes.
+            uint32_t n0 = 0u, n1 = 0u;  // counters of levels 0-7 and 8-15
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) {
+                const uint32_t inc = chain0 + ch < C ? 1u << (4 * (knew[ch] & 7)) : 0u;
+                if (knew[ch] < 8) n0 += inc;
+                else n1 += inc;
+            }
+            if (tpp >= 2) {
+                n0 += (uint32_t)__builtin_amdgcn_mov_dpp((int)n0, 0xB1, 0xF, 0xF, false);
+                n1 += (uint32_t)__builtin_amdgcn_mov_dpp((int)n1, 0xB1, 0xF, 0xF, false);
+            }
+            if (tpp == 4) {
+                n0 += (uint32_t)__builtin_amdgcn_mov_dpp((int)n0, 0x4E, 0xF, 0xF, false);
+                n1 += (uint32_t)__builtin_amdgcn_mov_dpp((int)n1, 0x4E, 0xF, 0xF, false);
+            }
+#pragma unroll
+            for (int w = 0; w < 8; ++w) {
+                if (w < hist_words && (w & (tpp - 1)) == grp) {
+                    const uint32_t byte = ((w < 4 ? n0 : n1) >> (8 * (w & 3))) & 0xFFu;  // levels 2w, 2w+1
+                    const uint32_t v = (byte & 0xFu) | ((byte >> 4) << 16);
+                    if (v != 0u) hrow[w] += v;
+                }
+            }
+        } else if (SUB == 1 && (tpp == 1 || tpp == 2 || tpp == 4)) {
+            // L <= 16, more chains: the pixel's whole counter row (at most 8 words) is built in registers,
             // summed across the pixel's lanes with DPP and added to memory by plain
             // read-modify-writes, one word per lane: no global atomics, which are performed
             // beyond the L2 here and would dominate a sweep with so few levels.
-            const int nw = a.hist_words;
+            const int nw = hist_words;
             uint32_t row[8];
 #pragma unroll
             for (int w = 0; w < 8; ++w) row[w] = 0u;
 #pragma unroll
             for (int ch = 0; ch < G; ++ch) {
-                const int wi = chain0 + ch < a.C ? knew[ch] >> 1 : -1;
+                const int wi = chain0 + ch < C ? knew[ch] >> 1 : -1;
                 const uint32_t inc = (knew[ch] & 1) ? 0x10000u : 1u;
 #pragma unroll
                 for (int w = 0; w < 8; ++w)
@@ -611,10 +753,65 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         } else {
 #pragma unroll
             for (int ch = 0; ch < G; ++ch) {
-                if (chain0 + ch < a.C) atomicAdd(hrow + (knew[ch] >> 1), 1u << (16 * (knew[ch] & 1)));
+                if (chain0 + ch < C) atomicAdd(hrow + (knew[ch] >> 1), 1u << (16 * (knew[ch] & 1)));
             }
         }
     }
+}
+
+// One thread's site updates of a sweep over state in global memory: pixel (r, c) = pix,
+// chains grp*G .. grp*G+G-1 (see site_draw).
+template <int G, int NBR, int SUB, int NBLK, int SHARE, bool INR = false>
+__device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab, SweepConsts kc, int pix, int r,
+                                           int c, int grp, int q)
+{
+    const int cofs = grp * G;
+    SiteInputs<NBR> in;
+    in.gp = a.gp[pix];
+    const uint8_t *xin = a.xin;
+    in.own = load_group<G>(xin + (int64_t)pix * a.Cp + cofs);
+#pragma unroll
+    for (int j = 0; j < NBR; ++j) {
+        const int rr = r + kNbrDr[j], cc = c + kNbrDc[j];
+        in.present[j] = rr >= 0 && rr < a.H && cc >= 0 && cc < a.W;
+        in.nbw[j] = in.present[j] ? load_group<G>(xin + ((int64_t)rr * a.W + cc) * a.Cp + cofs) : 0u;
+    }
+    int knew[G];
+    const uint32_t packed = site_draw<G, NBR, SUB, NBLK, SHARE, INR>(a, ptab, kc, in, pix, grp, q, knew);
+    store_group<G>(a.xout + (int64_t)pix * a.Cp + cofs, packed);
+    site_stats<G, SUB>(a.sum ? a.sum + pix : nullptr, a.hist ? a.hist + (int64_t)pix * a.hist_words : nullptr,
+                       a.hist_words, a.C, a.Cp / G, grp, knew);
+}
+
+inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
+
+// Site of this thread in a single-lattice sweep (layout of SweepLayout); false if the
+// thread has none (past the last pixel, or outside the lattice in an edge tile).  All
+// threads of a pixel are consecutive lanes starting at a multiple of tpp.
+__device__ __forceinline__ bool sweep_thread_site(const SweepArgs &a, int tpp, int &pix, int &r, int &c, int &grp)
+{
+    const int64_t blk = a.blk0 + blockIdx.x;
+    const int t = (int)threadIdx.x;
+    if (a.patch >= 0) {
+        const int lp = 6 - a.patch, lr = lp >> 1, lc = lp - lr;
+        const int b = (int)blk;  // fewer than 2^31 workgroups
+        const int tr = b / a.tiles_w, tc = b - tr * a.tiles_w;
+        const int w = t >> 6;               // wave of the workgroup: 2x2 patches
+        const int p = (t & 63) >> a.patch;  // pixel within the wave's patch
+        grp = t & (tpp - 1);
+        r = (((tr << 1) + (w >> 1)) << lr) + (p >> lc);
+        c = (((tc << 1) + (w & 1)) << lc) + (p & ((1 << lc) - 1));
+        if (r >= a.H || c >= a.W) return false;
+        pix = r * a.W + c;
+        return true;
+    }
+    const int64_t gid = blk * kBlock + t;
+    if (gid >= (int64_t)a.H * a.W * tpp) return false;
+    pix = (int)(gid / tpp);
+    grp = (int)(gid - (int64_t)pix * tpp);
+    r = pix / a.W;
+    c = pix - r * a.W;
+    return true;
 }
 
 // ---------------------------------------------------------------- batched sweep
@@ -666,12 +863,11 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
     const int local = blk - d.block_base;
     int pix, r, c, grp;
     if constexpr (TILED == 0) {
-        const int64_t gid = (int64_t)local * kBlock + threadIdx.x;
-        if (gid >= (int64_t)d.H * d.W * tpp) return;
-        pix = (int)(gid / tpp);
-        grp = (int)(gid - (int64_t)pix * tpp);
-        r = pix / d.W;
-        c = pix - r * d.W;
+        // row-major, or 2-D pixel patches for L > 16, laid out as in a single-lattice sweep
+        a.patch = d.patch;
+        a.tiles_w = d.tiles_w;
+        a.blk0 = (int64_t)local - (int64_t)blockIdx.x;
+        if (!sweep_thread_site(a, tpp, pix, r, c, grp)) return;
     } else {
         const int th = kBlock / tpp / kTileW;  // tile height in pixels
         const int tr = local / d.tiles_w, tc = local - (local / d.tiles_w) * d.tiles_w;
@@ -688,37 +884,6 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
     const int q = (int)(threadIdx.x % SHARE);
     if (a.L <= 16) sweep_site<G, NBR, 1, 16, SHARE, INR>(a, ptab, kc, pix, r, c, grp, q);
     else sweep_site<G, NBR, 16, 16, SHARE, INR>(a, ptab, kc, pix, r, c, grp, q);
-}
-
-inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
-
-// Site of this thread in a single-lattice sweep (layout of SweepLayout); false if the
-// thread has none (past the last pixel, or outside the lattice in an edge tile).  All
-// threads of a pixel are consecutive lanes starting at a multiple of tpp.
-__device__ __forceinline__ bool sweep_thread_site(const SweepArgs &a, int tpp, int &pix, int &r, int &c, int &grp)
-{
-    const int64_t blk = a.blk0 + blockIdx.x;
-    const int t = (int)threadIdx.x;
-    if (a.patch >= 0) {
-        const int lp = 6 - a.patch, lr = lp >> 1, lc = lp - lr;
-        const int b = (int)blk;  // fewer than 2^31 workgroups
-        const int tr = b / a.tiles_w, tc = b - tr * a.tiles_w;
-        const int w = t >> 6;               // wave of the workgroup: 2x2 patches
-        const int p = (t & 63) >> a.patch;  // pixel within the wave's patch
-        grp = t & (tpp - 1);
-        r = (((tr << 1) + (w >> 1)) << lr) + (p >> lc);
-        c = (((tc << 1) + (w & 1)) << lc) + (p & ((1 << lc) - 1));
-        if (r >= a.H || c >= a.W) return false;
-        pix = r * a.W + c;
-        return true;
-    }
-    const int64_t gid = blk * kBlock + t;
-    if (gid >= (int64_t)a.H * a.W * tpp) return false;
-    pix = (int)(gid / tpp);
-    grp = (int)(gid - (int64_t)pix * tpp);
-    r = pix / a.W;
-    c = pix - r * a.W;
-    return true;
 }
 
 // Waves per SIMD the single-lattice sweep kernels are compiled for.  With 16-level blocks
