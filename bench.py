@@ -37,6 +37,7 @@ PEAK_VALU_TOPS = 256 * 128 * 2.4e9 / 1e12
 PEAK_HBM_GBS = 8000.0
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2507_14869_amd", "csrc", f) for f in ("pca_sweep.h", "pca_kernels.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_c3_traffic.txt")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "sweep_kernel_c3_counters.txt")
 
 
 def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0, nbr: int = 4) -> float:
@@ -49,6 +50,13 @@ def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0, nbr: in
     if inertia:
         return levels * (sads + 18.0 + 2.0 / chains)
     return levels * (sads + 3.0 + 15.0 / chains)
+
+
+def model_bytes_per_site_update(chains: int) -> float:
+    """HBM bytes the method must move per site update on an accumulating sweep: state read
+    and write (2 per chain), observation read (4 per pixel) and the uint32 sum
+    read-modify-write (8 per pixel), i.e. 2 + 12/C."""
+    return 2.0 + 12.0 / chains
 
 
 def hbm_bytes_per_sweep(N: int, chains: int, acc: bool, tally: bool) -> float:
@@ -101,6 +109,24 @@ def measured_traffic(per_launch_units: float):
         return None
 
 
+def measured_valu_per_site_update():
+    """VALU instructions per site update of the sweep kernel from the committed rocprofv3
+    counter summary (SQ_INSTS_VALU per wave / site updates per wave) when it was taken on
+    the current kernel source; otherwise None."""
+    if not os.path.exists(COUNTERS_FILE):
+        return None
+    txt = open(COUNTERS_FILE).read()
+    if f"sha256[:16] = {kernel_hash()}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith("# VALU instructions per wave") and "per site update:" in line:
+            try:
+                return float(line.rsplit(":", 1)[1])
+            except ValueError:
+                return None
+    return None
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as f:
@@ -113,37 +139,101 @@ def cpu_model() -> str:
 
 
 def cpu_baseline(wl, seconds: float, inertia: int = 0, threads: int = 1):
-    """The oracle on sampled site updates of sweep 0 of the same workload, in `threads`
-    host threads (the oracle's C code runs outside the interpreter lock), each drawing its
-    own random (chain, pixel) sample for `seconds`."""
-    import numpy as np
+    """The oracle timed on this host's cores on a bounded sample of the same job.  When a
+    whole sweep fits in a third of `seconds`, whole sweeps of the job from its initial
+    state (the oracle's own run, with its accumulators); otherwise row bands of every chain
+    of sweep 0.  With threads > 1 the row bands are spread over a pool of host threads (the
+    oracle's C code runs outside the interpreter lock)."""
     from concurrent.futures import ThreadPoolExecutor
     import oracle
     p = oracle.Params(**wl.params(inertia=inertia))
     x0 = oracle.init_state(p, wl.obs)
-    N = wl.height * wl.width
-
-    def worker(seed):
-        rng = np.random.default_rng(seed)
-        done = 0
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds:
-            n = 4096
-            ch = rng.integers(0, wl.chains, n).astype(np.int32)
-            px = rng.integers(0, N, n).astype(np.int64)
-            oracle.update_sites(p, wl.obs, x0, 0, ch, px)
-            done += n
-        return done, time.perf_counter() - t0
-
-    with ThreadPoolExecutor(max_workers=threads) as pool:
-        res = list(pool.map(worker, [7 + i for i in range(threads)]))
-    done = sum(r[0] for r in res)
-    dt = max(r[1] for r in res)
+    band = 8
+    t0 = time.perf_counter()
+    oracle.pca_rows(p, wl.obs, x0, 0, 0, 0, min(band, wl.height))
+    per_sweep = (time.perf_counter() - t0) * wl.height / min(band, wl.height) * wl.chains / threads
     how = "single-threaded" if threads == 1 else f"in {threads} threads"
+    if per_sweep <= seconds / 3:
+        run = oracle.Run(p, wl.obs)
+        k = 0
+        t0 = time.perf_counter()
+        while k < wl.sweeps and time.perf_counter() - t0 < seconds:
+            if threads == 1:
+                run.sweep(1)
+            else:
+                run.state = oracle.pca_sweep_threaded(p, wl.obs, run.state, run.t, threads=threads)
+                run.t += 1
+            k += 1
+        dt = time.perf_counter() - t0
+        done = k * wl.height * wl.width * wl.chains
+        sample = f"{k} whole sweeps of the {wl.height}x{wl.width} L={wl.levels} job from its initial state"
+    else:
+        jobs = [(ch, r0) for r0 in range(0, wl.height, band) for ch in range(wl.chains)]
+        done_rows = []
+        t0 = time.perf_counter()
+
+        def one(job):
+            if time.perf_counter() - t0 >= seconds:
+                return 0
+            ch, r0 = job
+            r1 = min(r0 + band, wl.height)
+            oracle.pca_rows(p, wl.obs, x0, 0, ch, r0, r1)
+            return r1 - r0
+
+        with ThreadPoolExecutor(max_workers=threads) as pool:
+            done_rows = list(pool.map(one, jobs))
+        dt = time.perf_counter() - t0
+        done = sum(done_rows) * wl.width
+        sample = (f"{sum(done_rows)} rows ({band}-row bands, every chain) of sweep 0 of the {wl.height}x{wl.width} "
+                  f"L={wl.levels} job")
     return {"value": done / dt, "unit": "site-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{done} random (chain, pixel) site updates of sweep 0 of the same {wl.height}x{wl.width} "
-                      f"L={wl.levels} workload, {dt:.1f} s {how}",
+            "sample": f"{sample}: {done} site updates in {dt:.1f} s {how}",
             "cpu_model": cpu_model(), "host_cpus": os.cpu_count()}
+
+
+def quality(wl, mean, mpm):
+    """PSNR and SSIM (windowed and the paper's single-window form) of the posterior mean and
+    of the marginal mode against the ground truth, and of the noisy observation, all on
+    luminance in [0, 1] (Sec. 6)."""
+    import numpy as np
+    from workloads import metrics
+    truth = metrics.luminance_levels(wl.truth, wl.levels)
+    noisy = metrics.luminance_values(np.clip(wl.obs, wl.vmin, wl.vmax), wl.vmin, wl.vmax)
+    out = {}
+    for name, img in (("observation", noisy), ("posterior_mean", metrics.luminance_values(mean, wl.vmin, wl.vmax)),
+                      ("marginal_mode", None if mpm is None else metrics.luminance_levels(mpm, wl.levels))):
+        if img is None:
+            continue
+        out[name] = {"psnr_db": metrics.psnr(truth, img), "ssim": metrics.ssim_windowed(truth, img),
+                     "ssim_global": metrics.ssim_global(truth, img)}
+    return out
+
+
+def gibbs_comparison(wl):
+    """The sequential single-site Gibbs sampler of Sec. 5.1 on the CPU (the oracle's), run
+    for the same sweeps on the same data with the same seed: the paper's comparison
+    (Table 1).  Returns its time and the quality of its posterior mean and mode."""
+    import oracle
+    p = oracle.Params(**wl.params())
+    t0 = time.perf_counter()
+    run = oracle.Run(p, wl.obs, gibbs=True).sweep(wl.sweeps)
+    dt = time.perf_counter() - t0
+    q = quality(wl, run.posterior_mean(), run.marginal_map() if wl.tally_stride > 0 else None)
+    q.pop("observation", None)
+    return {"sweeps": wl.sweeps, "seconds": dt, "cores": 1,
+            "site_updates_per_s": wl.height * wl.width * wl.chains * wl.sweeps / dt, **q}
+
+
+def workload_label(wl, inertia: int) -> str:
+    if wl.prior == 0:
+        prior = f"Potts prior J={wl.J} (2J per disagreeing neighbour)"
+    else:
+        prior = f"truncated-linear prior T={wl.trunc} J={wl.J}"
+    scale = (wl.levels - 1) / (wl.vmax - wl.vmin)
+    sig = f"sigma={wl.sigma:g} levels" if scale == 1.0 else f"sigma={wl.sigma:g} in value units ({wl.sigma * scale:g} levels)"
+    return (f"{wl.name}: {wl.height}x{wl.width} image, L={wl.levels}, {wl.chains} chains, {wl.sweeps} sweeps, "
+            f"{prior}, q={wl.q}, {sig}, {wl.neighbourhood}-neighbour, mean + marginal mode"
+            + ("" if inertia == 0 else f", L{inertia} inertia"))
 
 
 def copy_probe(mib: int, reps: int = 4):
@@ -247,9 +337,12 @@ def bench_serve(args):
     """Poisson arrivals at 50 requests/s (sides log-uniform in [64, 4096], L in {2, 16, 256},
     sigma ~ U[0.1, 0.3] L, 2 chains, 300 sweeps) through the continuous-batching server, and
     through a one-request-at-a-time baseline on the same trace.  Latency is measured from
-    each request's scheduled arrival to the end of the step that finished it.  With
-    --shed-backlog-s the server refuses submissions while its predicted wait exceeds the
-    limit; latency, throughput and quality are then over the requests it served."""
+    each request's scheduled arrival to the end of the step that finished it.  The offered
+    load rho is the arrival rate times the mean time a request takes on the GPU alone
+    (measured in the one-at-a-time run).  The same requests are then served saturated (all
+    arriving at once), both ways.  With --shed-backlog-s the server refuses submissions while
+    its predicted wait exceeds the limit; latency, throughput and quality are then over the
+    requests it served."""
     import numpy as np
     import torch
     from paper_2507_14869_amd import PCA_EBUSY, PcaError, Sampler, Server
@@ -263,18 +356,19 @@ def bench_serve(args):
         kw.pop("height")
         kw.pop("width")
         kws.append(kw)
-    su_total = sum(w.height * w.width * w.chains for w in reqs) * sweeps
+    su_of = [w.height * w.width * w.chains * sweeps for w in reqs]
+    su_total = sum(su_of)
 
-    def run_server():
+    def run_server(arrive, shed_s):
         sv = Server(160 << 30, max_active=512, sweeps_per_step=sweeps, step_ms=args.step_ms)
-        sv.set_shedding(args.shed_backlog_s)
+        sv.set_shedding(shed_s)
         done_at, rid_of = {}, {}
         i = 0
         t0 = time.perf_counter()
         busy = 0.0
         while len(done_at) < len(rid_of) or i < len(reqs):
             now = time.perf_counter() - t0
-            while i < len(reqs) and arrivals[i] <= now:
+            while i < len(reqs) and arrive[i] <= now:
                 try:
                     rid_of[sv.submit(reqs[i].obs, sweeps, **kws[i])] = i
                 except PcaError as err:  # refused by the shedding limit
@@ -284,7 +378,7 @@ def bench_serve(args):
             q, a, _, _, _ = sv.stats()
             if q == 0 and a == 0:
                 if i < len(reqs):
-                    time.sleep(max(0.0, min(arrivals[i] - now, 0.05)))
+                    time.sleep(max(0.0, min(arrive[i] - now, 0.05)))
                 continue
             ts = time.perf_counter()
             sv.step()
@@ -299,23 +393,34 @@ def bench_serve(args):
         steps = sv.stats()[3]
         sv.close()
         served = sorted(results)
-        lat = np.array([done_at[k] - arrivals[k] for k in served])
-        return lat, makespan, busy, steps, results, served
+        lat = np.array([done_at[k] - arrive[k] for k in served])
+        return {"lat": lat, "makespan": makespan, "busy": busy, "steps": steps, "results": results, "served": served}
 
-    def run_sequential():
-        done_at = {}
+    def run_sequential(arrive):
+        done_at, service, means = {}, {}, {}
         t0 = time.perf_counter()
         for k, w in enumerate(reqs):
             now = time.perf_counter() - t0
-            if arrivals[k] > now:
-                time.sleep(arrivals[k] - now)
+            if arrive[k] > now:
+                time.sleep(arrive[k] - now)
+            ts = time.perf_counter()
             s = Sampler(torch.from_numpy(w.obs).cuda(), **kws[k]).sweep(sweeps)
-            s.posterior_mean().cpu()
+            means[k] = s.posterior_mean().cpu().numpy()
             s.close()
-            done_at[k] = time.perf_counter() - t0
+            te = time.perf_counter()
+            service[k] = te - ts
+            done_at[k] = te - t0
         makespan = time.perf_counter() - t0
-        lat = np.array([done_at[k] - arrivals[k] for k in range(len(reqs))])
-        return lat, makespan
+        lat = np.array([done_at[k] - arrive[k] for k in range(len(reqs))])
+        return {"lat": lat, "makespan": makespan, "service": service, "results": means}
+
+    def pct(lat):
+        return {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                "mean": float(lat.mean()), "max": float(lat.max())}
+
+    def psnr_of(k, img):
+        w = reqs[k]
+        return metrics.psnr(metrics.luminance_levels(w.truth, w.levels), metrics.luminance_values(img, w.vmin, w.vmax))
 
     # warm up the library and the kernels
     warm = Server(1 << 33, 8, 30)
@@ -325,24 +430,28 @@ def bench_serve(args):
     warm.close()
     torch.cuda.synchronize()
 
-    lat, makespan, busy, steps, results, served = run_server()
-    su_served = sum(reqs[k].height * reqs[k].width * reqs[k].chains for k in served) * sweeps
-    lat_seq, makespan_seq = run_sequential()
-    psnr_gain = []
+    srv = run_server(arrivals, args.shed_backlog_s)
+    served = srv["served"]
+    su_served = sum(su_of[k] for k in served)
+    seq = run_sequential(arrivals)
+    mean_service = float(np.mean(list(seq["service"].values())))
+    rate = len(reqs) / float(arrivals[-1])
+    psnr_gain, psnr_delta = [], []
     for k in served:
         w = reqs[k]
-        truth = metrics.luminance_levels(w.truth, w.levels)
         noisy = metrics.luminance_values(np.clip(w.obs, w.vmin, w.vmax), w.vmin, w.vmax)
-        est = metrics.luminance_values(results[k], w.vmin, w.vmax)
-        psnr_gain.append(metrics.psnr(truth, est) - metrics.psnr(truth, noisy))
+        truth = metrics.luminance_levels(w.truth, w.levels)
+        p_served = psnr_of(k, srv["results"][k])
+        psnr_gain.append(p_served - metrics.psnr(truth, noisy))
+        psnr_delta.append(abs(p_served - psnr_of(k, seq["results"][k])))
     out = {
         "metric": "site-updates/s",
-        "value": su_served / makespan,
+        "value": su_served / srv["makespan"],
         "unit": "site-updates/s",
         "n_gpus": 1,
         "steps": 1,
         "warmup": 1,
-        "ms_per_step": makespan * 1e3,
+        "ms_per_step": srv["makespan"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -353,20 +462,31 @@ def bench_serve(args):
                         f"L in {{2, 16, 256}}, 2 chains, {sweeps} sweeps, continuous batching, {args.step_ms} ms steps",
             "requests": len(reqs), "site_updates": su_total,
         },
+        "offered_load": {"rho": rate * mean_service, "arrival_rate_per_s": rate,
+                         "mean_service_s": mean_service,
+                         "service": "time of one request alone on the GPU (one-at-a-time run, upload to mean "
+                                    "download)"},
         "shedding": {"max_backlog_s": args.shed_backlog_s, "served": len(served), "shed": len(reqs) - len(served),
                      "shed_fraction": 1.0 - len(served) / len(reqs)},
-        "latency_s": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                      "mean": float(lat.mean()), "max": float(lat.max())},
-        "requests_per_s": len(served) / makespan,
-        "gpu_busy_fraction": busy / makespan,
-        "server_steps": steps,
+        "latency_s": pct(srv["lat"]),
+        "requests_per_s": len(served) / srv["makespan"],
+        "gpu_busy_fraction": srv["busy"] / srv["makespan"],
+        "server_steps": srv["steps"],
         "mean_psnr_gain_db": float(np.mean(psnr_gain)),
-        "one_request_at_a_time": {
-            "value": su_total / makespan_seq,
-            "latency_s": {"p50": float(np.percentile(lat_seq, 50)), "p99": float(np.percentile(lat_seq, 99)),
-                          "mean": float(lat_seq.mean())},
-        },
+        "max_psnr_delta_vs_alone_db": float(np.max(psnr_delta)),
+        "one_request_at_a_time": {"value": su_total / seq["makespan"], "latency_s": pct(seq["lat"])},
     }
+    if args.shed_backlog_s == 0.0:
+        # saturated: every request waiting at time 0
+        zero = np.zeros(len(reqs))
+        srv0 = run_server(zero, 0.0)
+        seq0 = run_sequential(zero)
+        out["saturated"] = {
+            "served": {"value": su_total / srv0["makespan"], "makespan_s": srv0["makespan"],
+                       "latency_s": pct(srv0["lat"]), "server_steps": srv0["steps"]},
+            "one_request_at_a_time": {"value": su_total / seq0["makespan"], "makespan_s": seq0["makespan"],
+                                      "latency_s": pct(seq0["lat"])},
+        }
     print(json.dumps(out), flush=True)
 
 
@@ -377,7 +497,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--requests", type=int, default=250, help="c5: number of requests in the trace")
-    ap.add_argument("--step-ms", type=float, default=20.0, help="c5: GPU time per server step")
+    ap.add_argument("--step-ms", type=float, default=50.0, help="c5: GPU time per server step")
     ap.add_argument("--shed-backlog-s", type=float, default=0.0,
                     help="c5: refuse submissions while the predicted wait exceeds this (0: never)")
     ap.add_argument("--sweeps", type=int, default=None, help="override the workload's sweep count")
@@ -485,10 +605,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"{wl.name}: {wl.height}x{wl.width} image, L={wl.levels}, {wl.chains} chains, "
-                        f"{wl.sweeps} sweeps, truncated-linear prior T={wl.trunc} J={wl.J} q={wl.q}, "
-                        f"sigma={wl.sigma} levels, {wl.neighbourhood}-neighbour, mean + marginal mode"
-                        + ("" if args.inertia == 0 else f", L{args.inertia} inertia"),
+            "workload": workload_label(wl, args.inertia),
             "inertia": args.inertia,
             "height": wl.height, "width": wl.width, "levels": wl.levels, "chains": wl.chains,
             "sweeps": wl.sweeps, "site_updates_per_step": wl.site_updates,
@@ -502,13 +619,22 @@ def main():
             "traffic": traffic,
             "kernel": "sweep_kernel",
             "ops_per_site_update": ops_per_su,
+            "ops_model": "dense-equivalent: every level of every chain counted as a full evaluation (levels "
+                         "where no chain of a wave is near a neighbour's level, which the kernel handles with "
+                         "one fma per chain, are counted in full)",
             "avg_launch_ms": avg_launch_s * 1e3,
+            "peak_note": "32-bit VALU issue rate, 256 CUs x 128 lanes x 2.4 GHz (the FP32 vector peak counts "
+                         "an fma as two flops); the kernel's integer VOP3 instructions (byte SADs, 24-bit mads, "
+                         "shift-adds) are 5 of its 7 per (chain, level)",
         },
         "hbm": {
             "algorithmic_bytes_per_launch": hbm_alg,
             "achieved_GBs": hbm_alg / avg_launch_s / 1e9,
             "peak_GBs": PEAK_HBM_GBS,
             "frac": hbm_alg / avg_launch_s / 1e9 / PEAK_HBM_GBS,
+            "model_bytes_per_site_update": model_bytes_per_site_update(wl.chains),
+            "frac_at_model_bytes": model_bytes_per_site_update(wl.chains) * N * wl.chains / avg_launch_s / 1e9
+                                   / PEAK_HBM_GBS,
         },
         "level_evaluations_per_s": value * wl.levels,
     }
@@ -527,8 +653,22 @@ def main():
     s.close()
     out["end_to_end"] = {"ms_per_job": e2e * 1e3, "site_updates_per_s": wl.site_updates / e2e,
                          "includes": "observation upload from host memory, the job, mean and mode download"}
+    same_kernel_work = wl.name == "c3" and args.inertia == 0 and wl.neighbourhood == 4 and args.q is None
+    issue = measured_valu_per_site_update() if same_kernel_work else None
+    if issue is not None:
+        # instructions the kernel issued (rocprofv3 SQ_INSTS_VALU x 64 lanes, same kernel source)
+        lane_insts = issue * N * wl.chains
+        out["roofline"]["measured_issue"] = {
+            "valu_instructions_per_site_update": issue,
+            "achieved": lane_insts / avg_launch_s / 1e12,
+            "frac": lane_insts / avg_launch_s / 1e12 / PEAK_VALU_TOPS,
+            "source": os.path.relpath(COUNTERS_FILE, ROOT),
+        }
+    out["quality"] = quality(wl, mean.cpu().numpy(), None if mpm is None else mpm.cpu().numpy())
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.inertia)
+        if wl.name == "c1" and args.inertia == 0:
+            out["cpu_baseline"]["gibbs"] = gibbs_comparison(wl)
         threads = min(16, len(os.sched_getaffinity(0)))
         if threads > 1:
             out["cpu_baseline_all_cores"] = cpu_baseline(wl, args.cpu_seconds, args.inertia, threads)
