@@ -1,0 +1,48 @@
+"""Several sweeps per launch (lattices with L <= 16 too small to fill the GPU: each
+workgroup advances an LDS tile with a halo as deep as the sweeps it runs) against the CPU
+oracle.  The runs cross every boundary inside a launch: the beta schedule changes at
+every sweep for the first twelve (the prior table is rebuilt inside a launch), burn-in ends
+and tally sweeps fall in the middle of one, and 21 sweeps split into launches of 8, 8 and 5.
+Lattice shapes give ragged edge tiles, 1x1 and one-row lattices, and chain counts whose
+pixels take 1, 2 or 3 threads (3: no lane sharing, LDS and global atomics for the tallies).
+States, posterior means and marginal modes must be identical."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import gpu_sampler, oracle_run, torch_cuda
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("case", [
+    # (H, W, L, chains, nbr, prior, T)
+    (1, 1, 4, 1, 4, 1, 2),
+    (1, 45, 16, 4, 8, 1, 4),
+    (5, 3, 16, 12, 8, 1, 3),     # 3 threads per pixel
+    (33, 29, 5, 6, 4, 1, 2),     # ragged 4x4 tiles, padded chain slots
+    (64, 64, 2, 1, 4, 0, 1),     # the binary workload's shape
+    (17, 70, 16, 8, 8, 1, 4),
+    (40, 40, 9, 2, 4, 0, 1),
+    (128, 128, 16, 4, 4, 1, 4),  # 16x16 tiles
+])
+def test_several_sweeps_per_launch_match_the_oracle(orc, case):
+    torch_cuda()
+    H, W, L, C, nbr, prior, T = case
+    rng = np.random.default_rng(H * 131 + W * 7 + C)
+    truth = synth.random_image(H, W, L, max(2, H * W // 300), L > 2, rng)
+    obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), 0.25 * L, rng)
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=nbr, prior=prior, trunc=T, J=0.35, q=1.1,
+              sigma=0.25 * L, vmin=0.0, vmax=float(L - 1), beta=[0.8 + 0.1 * i for i in range(12)],
+              seed=900 + H + W, burn_in=3, tally_stride=2)
+    ref = oracle_run(orc, obs, **kw).sweep(21)
+    gpu = gpu_sampler(obs, **kw).sweep(21)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+    # and split differently: 5 + 1 + 15 sweeps
+    gpu2 = gpu_sampler(obs, **kw).sweep(5).sweep(1).sweep(15)
+    assert np.array_equal(gpu2.state().cpu().numpy(), ref.state)
+    assert np.array_equal(gpu2.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    gpu.close()
+    gpu2.close()
