@@ -668,9 +668,18 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
 // word), its chains' uint16 counters into the pixel's histogram row hrow (either may be
 // null).  The tpp threads of a pixel are consecutive lanes; chains >= C (padding) count
 // nothing.
+// Words a thread updates, loaded before the level loop so their load latency overlaps it
+// (valid = false: site_stats loads them itself).  Safe because no other thread of the
+// launch writes them: each counter word and each pixel's sum has one owner.
+struct StatsPrefetch {
+    bool valid;
+    uint32_t sum;      // the pixel's level sum (when this lane updates it)
+    uint32_t row[8];   // the lane's histogram words, indexed by word (L <= 16 row path)
+};
+
 template <int G, int SUB>
 __device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hist_words, int C, int tpp, int grp,
-                                           const int (&knew)[G])
+                                           const int (&knew)[G], const StatsPrefetch &pf = StatsPrefetch{false, 0u, {}})
 {
     const int chain0 = grp * G;
     if (sum) {
@@ -682,11 +691,11 @@ __device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hi
         // with DPP and let the first lane update the word, instead of one atomic per lane
         // (global atomics are performed past L2, one memory write each).
         if (tpp == 1) {
-            *sum += lsum;
+            *sum = (pf.valid ? pf.sum : *sum) + lsum;
         } else if (tpp == 2 || tpp == 4) {
             uint32_t s = lsum + (uint32_t)__builtin_amdgcn_mov_dpp((int)lsum, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
             if (tpp == 4) s += (uint32_t)__builtin_amdgcn_mov_dpp((int)s, 0x4E, 0xF, 0xF, false);      // [2,3,0,1]
-            if (grp == 0) *sum += s;
+            if (grp == 0) *sum = (pf.valid ? pf.sum : *sum) + s;
         } else {
             atomicAdd(sum, lsum);
         }
@@ -717,7 +726,7 @@ __device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hi
                 if (w < hist_words && (w & (tpp - 1)) == grp) {
                     const uint32_t byte = ((w < 4 ? n0 : n1) >> (8 * (w & 3))) & 0xFFu;  // levels 2w, 2w+1
                     const uint32_t v = (byte & 0xFu) | ((byte >> 4) << 16);
-                    if (v != 0u) hrow[w] += v;
+                    if (v != 0u) hrow[w] = (pf.valid ? pf.row[w] : hrow[w]) + v;
                 }
             }
         } else if (SUB == 1 && (tpp == 1 || tpp == 2 || tpp == 4)) {
@@ -749,7 +758,7 @@ __device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hi
             }
 #pragma unroll
             for (int w = 0; w < 8; ++w)
-                if (w < nw && (w & (tpp - 1)) == grp && row[w] != 0u) hrow[w] += row[w];
+                if (w < nw && (w & (tpp - 1)) == grp && row[w] != 0u) hrow[w] = (pf.valid ? pf.row[w] : hrow[w]) + row[w];
         } else {
 #pragma unroll
             for (int ch = 0; ch < G; ++ch) {
@@ -776,11 +785,24 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         in.present[j] = rr >= 0 && rr < a.H && cc >= 0 && cc < a.W;
         in.nbw[j] = in.present[j] ? load_group<G>(xin + ((int64_t)rr * a.W + cc) * a.Cp + cofs) : 0u;
     }
+    // with few levels (a short level loop), the accumulator words this lane will update
+    // are loaded now (see StatsPrefetch); the 16-level-block kernels would spill them
+    const int tpp = a.Cp / G;
+    StatsPrefetch pf{SUB == 1, 0u, {}};
+    if constexpr (SUB == 1) {
+        if (a.sum && (tpp == 1 || ((tpp == 2 || tpp == 4) && grp == 0))) pf.sum = a.sum[pix];
+        if (a.hist && (tpp == 1 || tpp == 2 || tpp == 4)) {
+            const uint32_t *hrow = a.hist + (int64_t)pix * a.hist_words;
+#pragma unroll
+            for (int w = 0; w < 8; ++w)
+                if (w < a.hist_words && (w & (tpp - 1)) == grp) pf.row[w] = hrow[w];
+        }
+    }
     int knew[G];
     const uint32_t packed = site_draw<G, NBR, SUB, NBLK, SHARE, INR>(a, ptab, kc, in, pix, grp, q, knew);
     store_group<G>(a.xout + (int64_t)pix * a.Cp + cofs, packed);
     site_stats<G, SUB>(a.sum ? a.sum + pix : nullptr, a.hist ? a.hist + (int64_t)pix * a.hist_words : nullptr,
-                       a.hist_words, a.C, a.Cp / G, grp, knew);
+                       a.hist_words, a.C, tpp, grp, knew, pf);
 }
 
 inline unsigned grid_for(int64_t threads) { return (unsigned)((threads + kBlock - 1) / kBlock); }
