@@ -81,3 +81,34 @@ def test_static_run_refuses_a_run_above_its_working_memory():
     with pytest.raises(_lib.PcaError) as e:
         _lib.pca_run_static(p, obs.data_ptr(), 2, mean.data_ptr(), 0, 0)
     assert e.value.code == _lib.PCA_EINVAL
+
+
+def test_static_run_replays_from_a_captured_graph():
+    """The use it is for: pca_run_static captured into a HIP graph (it launches kernels only,
+    no allocation and no memset node) and replayed three times, with eager work on the
+    same outputs in between; every replay gives the eager call's bytes."""
+    torch = torch_cuda()
+    from paper_2507_14869_amd import _lib
+    obs, kw, sweeps = _case(64, 48, 16, 8, 12, 21, beta=[0.9, 1.0, 1.1])
+    H, W, C = kw["height"], kw["width"], kw["chains"]
+    want = _static_run(obs, kw, sweeps)  # eager, also looks the device array up before capture
+    dev_obs = torch.from_numpy(obs).cuda()
+    mean = torch.empty((H, W), dtype=torch.float32, device="cuda")
+    mpm = torch.empty((H, W), dtype=torch.uint8, device="cuda")
+    state = torch.empty((C, H, W), dtype=torch.uint8, device="cuda")
+    p, _buf = _lib.make_params(**kw)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        _lib.pca_run_static(p, dev_obs.data_ptr(), sweeps, mean.data_ptr(), mpm.data_ptr(), state.data_ptr(),
+                            torch.cuda.current_stream().cuda_stream)
+    for rep in range(3):
+        mean.fill_(float("nan"))
+        mpm.fill_(255)
+        state.fill_(255)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(mean.cpu().numpy().view(np.uint32), want[0].view(np.uint32)), rep
+        assert np.array_equal(mpm.cpu().numpy(), want[1]), rep
+        assert np.array_equal(state.cpu().numpy(), want[2]), rep
