@@ -224,6 +224,31 @@ def gibbs_comparison(wl):
             "site_updates_per_s": wl.height * wl.width * wl.chains * wl.sweeps / dt, **q}
 
 
+def gibbs_rate(wl, seconds: float):
+    """The oracle's sequential Gibbs sampler (Sec. 5.1, one thread, raster order) timed on
+    the same per-site work: whole sweeps of the workload's lattice, or of its top-left
+    128x128 crop when the lattice is larger, until `seconds` have passed (at least one
+    sweep)."""
+    import numpy as np
+    import oracle
+    H, W = wl.height, wl.width
+    if H * W > 128 * 128:
+        H, W = min(H, 128), min(W, 128)
+    p = oracle.Params(**{**wl.params(), "height": H, "width": W})
+    run = oracle.Run(p, np.ascontiguousarray(wl.obs[:H, :W]), gibbs=True)
+    k = 0
+    t0 = time.perf_counter()
+    while k == 0 or time.perf_counter() - t0 < seconds:
+        run.sweep(1)
+        k += 1
+    dt = time.perf_counter() - t0
+    su = k * H * W * wl.chains
+    where = "the whole lattice" if (H, W) == (wl.height, wl.width) else f"its top-left {H}x{W} crop"
+    return {"value": su / dt, "unit": "site-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"{k} sequential Gibbs sweeps of {where} ({wl.chains} chains, L={wl.levels}): "
+                      f"{su} site updates in {dt:.1f} s single-threaded"}
+
+
 def workload_label(wl, inertia: int) -> str:
     if wl.prior == 0:
         prior = f"Potts prior J={wl.J} (2J per disagreeing neighbour)"
@@ -669,6 +694,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.inertia)
         if wl.name == "c1" and args.inertia == 0:
             out["cpu_baseline"]["gibbs"] = gibbs_comparison(wl)
+        elif args.inertia == 0:
+            out["cpu_baseline"]["gibbs"] = gibbs_rate(wl, args.cpu_seconds / 2)
         threads = min(16, len(os.sched_getaffinity(0)))
         if threads > 1:
             out["cpu_baseline_all_cores"] = cpu_baseline(wl, args.cpu_seconds, args.inertia, threads)
