@@ -188,3 +188,18 @@ def test_tiled_batch_with_pixels_that_do_not_fill_a_tile(orc, chains, configs):
         assert np.array_equal(b.posterior_mean(0).cpu().numpy(), want.posterior_mean())
         assert np.array_equal(b.marginal_map(0).cpu().numpy(), want.marginal_map())
         b.close()
+
+
+def test_batch_patches_with_many_threads_per_pixel(orc):
+    """Untiled batched launches lay out L > 16 lattices in 2-D pixel patches; with 32 and 64
+    chains a pixel takes 8 and 16 threads (2x4 and 2x2-pixel patches per wave), mixed with a
+    row-major L = 2 lattice in the same launches: every lattice equals the oracle's run."""
+    problems = [_problem(23, 31, 40, 32, 41), _problem(9, 45, 256, 64, 42), _problem(30, 17, 2, 4, 43)]
+    b = _batch(problems)
+    b.set_config(4, 1, 0)
+    b.sweep(5)
+    for i, (obs, kw) in enumerate(problems):
+        ref = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(5)
+        assert np.array_equal(b.state(i).cpu().numpy(), ref.state), i
+        assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean()), i
+        assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map()), i
