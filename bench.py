@@ -355,7 +355,52 @@ def bench_batch(args):
         "one_launch_per_lattice": {"value": su / t_single, "ms_per_step": t_single * 1e3},
         "speedup_vs_one_launch_per_lattice": t_single / t_batch,
     }
+    out["small_lattices"] = bench_small_batch(sweeps)
     print(json.dumps(out), flush=True)
+
+
+def bench_small_batch(sweeps: int):
+    """A batch of 64 small lattices (sides log-uniform in [32, 128], L in {2, 16}, 4 chains),
+    whose sweeps are too short to fill the GPU: one launch per sweep (traversal 0) against
+    7 sweeps per launch from LDS tiles (traversal 2), and the autotuner's choice."""
+    import torch
+    from paper_2507_14869_amd import Batch
+    from workloads import synth
+    wls = synth.batch_mix(64, side_lo=32, side_hi=128, sweeps=sweeps, seed=1013, levels=(2, 16))
+    problems = []
+    for w in wls:
+        kw = w.params(burn_in=sweeps // 4, tally_stride=1)
+        kw.pop("height")
+        kw.pop("width")
+        problems.append((torch.from_numpy(w.obs).cuda(), kw))
+    su = sum(w.height * w.width * w.chains for w in wls) * sweeps
+
+    def job(cfg):
+        b = Batch(problems)
+        b.set_config(*cfg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.sweep(sweeps)
+        for i in range(len(problems)):
+            b.posterior_mean(i)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        return dt
+
+    tuner = Batch(problems)
+    tuner.autotune(3)
+    tuned = tuner.config
+    tuner.close()
+    res = {}
+    for name, cfg in (("one_sweep_per_launch", (4, 1, 0)), ("seven_sweeps_per_launch", (4, 1, 2)),
+                      ("autotuned", tuned)):
+        job(cfg)  # warm-up: graph capture
+        dt = min(job(cfg) for _ in range(3))
+        res[name] = {"config": list(cfg), "ms_per_job": dt * 1e3, "site_updates_per_s": su / dt}
+    res["workload"] = (f"64 lattices, sides log-uniform in [32, 128], L in {{2, 16}}, 4 chains, {sweeps} sweeps, "
+                       f"{su} site updates per job")
+    return res
 
 
 def bench_serve(args):

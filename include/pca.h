@@ -169,8 +169,10 @@ int pca_batch_init(const pca_params *params, const float *const *obs_dev, int32_
                    pca_batch **out);
 
 /* Launch-configuration autotuner: times every valid configuration (chains per thread
- * 1/2/4, lanes sharing a pixel's data factor 1/2/4, row-major or 16-pixel-wide tiled
- * traversal) over trial_sweeps (1..64) burn-in sweeps and trial_sweeps accumulating
+ * 1/2/4, lanes sharing a pixel's data factor 1/2/4, and the traversal: `tiled` 0 untiled -
+ * 2-D pixel patches for L > 16, row-major otherwise - 1 tiles 16 pixels wide, 2 as 0 but
+ * the lattices with L <= 16 advance 7 sweeps per launch from LDS tiles with halos) over
+ * trial_sweeps (1..64) burn-in sweeps and trial_sweeps accumulating
  * sweeps of this batch (each lattice from sweep 0 and from its burn-in length), in two
  * rounds, keeps the configuration with the smallest time of a round, then restores the
  * initial states (sweep index 0, accumulators cleared).  Synchronous.  *best_ms (may be

@@ -23,6 +23,8 @@ namespace {
 // the number of cached graphs stay bounded whatever n the caller passes.
 constexpr int32_t kGraphSweeps = 64;
 
+// tiled: 0 untiled (2-D patches for L > 16, else row-major), 1 tiles 16 pixels wide, 2 as 0
+// but lattices with L <= 16 run several sweeps per launch from LDS tiles.
 struct LaunchConfig {
     int G = 1, share = 1, tiled = 0;
     bool operator<(const LaunchConfig &o) const
@@ -57,6 +59,9 @@ struct pca_batch {
     pcak::ImageDesc *d_desc = nullptr;
     double *d_beta = nullptr;
     int *d_block_img = nullptr;
+    int *d_tb_block_img = nullptr;  // multi-sweep traversal: workgroup -> lattice
+    int tb_blocks = 0;
+    size_t tb_lds = 0;
     int64_t t = 0;
     LaunchConfig cfg;
     int total_blocks = 0;
@@ -67,16 +72,28 @@ struct pca_batch {
 
 namespace {
 
+// A lattice that the multi-sweep traversal takes: few levels, the indicator inertia, and a
+// tile with its halo within the LDS limit.
+bool multi_sweep_lattice(const pca_batch *b, const pcak::ImageDesc &d)
+{
+    return !b->inr && d.L <= 16 &&
+           pcak::tb_batch_lds_bytes(d.H, d.W, d.Cp, pcak::kTbBatchSide, pcak::kTbBatchSweeps, b->nbr * d.T + 1) <=
+               (size_t)pcak::kTbMaxLds;
+}
+
 bool config_valid(const pca_batch *b, const LaunchConfig &c)
 {
+    if (c.tiled < 0 || c.tiled > 2) return false;
     if (b->inr && c.share != 1) return false;  // each chain has its own exponent: nothing to share
+    bool any_multi = false;
     for (const auto &d : b->desc) {
         if (d.Cp % c.G != 0) return false;
         const int tpp = d.Cp / c.G;
         if (tpp % c.share != 0) return false;
-        if (c.tiled && (tpp > pcak::kBlock / pcak::kTileW)) return false;
+        if (c.tiled == 1 && (tpp > pcak::kBlock / pcak::kTileW)) return false;
+        any_multi = any_multi || multi_sweep_lattice(b, d);
     }
-    return true;
+    return c.tiled != 2 || any_multi;  // without such a lattice it would be configuration 0
 }
 
 std::vector<LaunchConfig> candidates(const pca_batch *b)
@@ -84,7 +101,7 @@ std::vector<LaunchConfig> candidates(const pca_batch *b)
     std::vector<LaunchConfig> out;
     for (int G : {4, 2, 1})
         for (int share : {4, 2, 1})
-            for (int tiled : {0, 1}) {
+            for (int tiled : {0, 1, 2}) {
                 LaunchConfig c{G, share, tiled};
                 if (config_valid(b, c)) out.push_back(c);
             }
@@ -100,14 +117,34 @@ void drop_graphs(pca_batch *b)
 // Lays out the batched grid for a launch configuration: workgroup ranges per lattice.
 int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
 {
-    std::vector<int> block_img;
+    std::vector<int> block_img, tb_block_img;
     int base = 0;
+    size_t tb_lds = 0;
     for (int i = 0; i < b->n; ++i) {
         pcak::ImageDesc &d = b->desc[i];
         d.tpp = d.Cp / c.G;
+        d.tb_side = 0;
+        if (c.tiled == 2 && multi_sweep_lattice(b, d)) {
+            // its own table of workgroups, one per LDS tile
+            const int side = pcak::kTbBatchSide;
+            d.tb_side = side;
+            d.patch = -1;
+            d.tiles_w = (d.W + side - 1) / side;
+            d.block_base = (int)tb_block_img.size();
+            const int64_t tiles = (int64_t)d.tiles_w * ((d.H + side - 1) / side);
+            if ((int64_t)tb_block_img.size() + tiles > 0x7FFFFFFF) return fail(PCA_EINVAL, "batch grid too large");
+            try {
+                tb_block_img.insert(tb_block_img.end(), (size_t)tiles, i);
+            } catch (const std::bad_alloc &) {
+                return fail(PCA_ENOMEM, "batch: host allocation failed");
+            }
+            tb_lds = std::max(tb_lds, pcak::tb_batch_lds_bytes(d.H, d.W, d.Cp, side, pcak::kTbBatchSweeps,
+                                                                b->nbr * d.T + 1));
+            continue;
+        }
         d.block_base = base;
         int blocks;
-        if (c.tiled) {
+        if (c.tiled == 1) {
             const int th = pcak::kBlock / d.tpp / pcak::kTileW;
             d.tiles_w = (d.W + pcak::kTileW - 1) / pcak::kTileW;
             d.patch = -1;
@@ -131,9 +168,17 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
     }
     (void)hipFree(b->d_block_img);
     b->d_block_img = nullptr;
-    hipError_t e = hipMalloc(&b->d_block_img, block_img.size() * sizeof(int));
+    (void)hipFree(b->d_tb_block_img);
+    b->d_tb_block_img = nullptr;
+    hipError_t e = block_img.empty() ? hipSuccess : hipMalloc(&b->d_block_img, block_img.size() * sizeof(int));
+    if (e == hipSuccess && !tb_block_img.empty()) e = hipMalloc(&b->d_tb_block_img, tb_block_img.size() * sizeof(int));
     if (e != hipSuccess) return fail(PCA_ENOMEM, "batch: allocation failed");
-    e = hipMemcpyAsync(b->d_block_img, block_img.data(), block_img.size() * sizeof(int), hipMemcpyHostToDevice, s);
+    if (!block_img.empty())
+        e = hipMemcpyAsync(b->d_block_img, block_img.data(), block_img.size() * sizeof(int), hipMemcpyHostToDevice,
+                           s);
+    if (e == hipSuccess && !tb_block_img.empty())
+        e = hipMemcpyAsync(b->d_tb_block_img, tb_block_img.data(), tb_block_img.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_desc, b->desc.data(), b->desc.size() * sizeof(pcak::ImageDesc), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -143,6 +188,8 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
     }
     b->cfg = c;
     b->total_blocks = base;
+    b->tb_blocks = (int)tb_block_img.size();
+    b->tb_lds = tb_lds;
     drop_graphs(b);
     return PCA_OK;
 }
@@ -198,6 +245,7 @@ void release(pca_batch *b)
     (void)hipFree(b->d_desc);
     (void)hipFree(b->d_beta);
     (void)hipFree(b->d_block_img);
+    (void)hipFree(b->d_tb_block_img);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
 }
@@ -222,11 +270,24 @@ int check_guards(const pca_batch *b, int32_t n, std::vector<int64_t> *add_count,
 
 int enqueue_eager(pca_batch *b, int32_t n, hipStream_t s)
 {
-    for (int32_t i = 0; i < n; ++i) {
-        pcak::BatchLaunch bl{b->d_desc, b->d_block_img, (uint32_t)i};
-        hipError_t e = pcak::launch_batch_sweep(bl, b->total_blocks, b->cfg.G, b->cfg.share, b->cfg.tiled, b->nbr,
-                                                b->inr, s);
-        if (e != hipSuccess) return hip_fail(e, "batch sweep");
+    for (int32_t i = 0; i < n;) {
+        // the multi-sweep lattices advance an odd number of sweeps per launch: 7, or what
+        // is left split into odd parts
+        const int32_t left = n - i;
+        const int32_t S = b->tb_blocks == 0 ? 1 : left >= pcak::kTbBatchSweeps ? pcak::kTbBatchSweeps
+                                                              : (left & 1) ? left : left - 1;
+        if (b->tb_blocks > 0) {
+            pcak::TbBatchLaunch tl{b->d_desc, b->d_tb_block_img, (uint32_t)i, S};
+            const hipError_t e = pcak::launch_tb_batch(tl, b->tb_blocks, b->cfg.G, b->cfg.share, b->nbr, b->tb_lds, s);
+            if (e != hipSuccess) return hip_fail(e, "batch sweep");
+        }
+        for (int32_t j = i; j < i + S && b->total_blocks > 0; ++j) {
+            pcak::BatchLaunch bl{b->d_desc, b->d_block_img, (uint32_t)j};
+            const hipError_t e = pcak::launch_batch_sweep(bl, b->total_blocks, b->cfg.G, b->cfg.share,
+                                                          b->cfg.tiled == 1 ? 1 : 0, b->nbr, b->inr, s);
+            if (e != hipSuccess) return hip_fail(e, "batch sweep");
+        }
+        i += S;
     }
     hipError_t e = pcak::launch_advance(b->d_desc, b->n, (uint32_t)n, s);
     return e == hipSuccess ? PCA_OK : hip_fail(e, "batch sweep");
@@ -439,7 +500,7 @@ int pca_batch_config(const pca_batch *b, int32_t *chains_per_thread, int32_t *sh
 int pca_batch_set_config(pca_batch *b, int32_t chains_per_thread, int32_t share, int32_t tiled, void *stream)
 {
     if (!b) return fail(PCA_EINVAL, "batch is NULL");
-    LaunchConfig c{chains_per_thread, share, tiled ? 1 : 0};
+    LaunchConfig c{chains_per_thread, share, tiled};
     if ((c.G != 1 && c.G != 2 && c.G != 4) || (c.share != 1 && c.share != 2 && c.share != 4) || !config_valid(b, c))
         return fail(PCA_EINVAL, "launch configuration not valid for this batch");
     b->last = (hipStream_t)stream;

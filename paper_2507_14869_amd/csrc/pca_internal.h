@@ -116,6 +116,7 @@ struct ImageDesc {
     int block_base;       // first workgroup of this lattice in the batched grid
     int tiles_w;          // tiled traversal: tiles per tile row; patch traversal: tiles per row
     int patch;            // untiled traversal: log2(tpp) if the pixels form 2-D patches, else -1
+    int tb_side;          // multi-sweep traversal: side of the lattice's square LDS tiles, else 0
     uint32_t t;           // sweep index before the current replay; advanced on the device
     uint32_t t_end;       // the lattice stops advancing at this sweep index
 };
@@ -179,6 +180,20 @@ struct TbPlan {
 
 TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia);
 hipError_t launch_tb_sweeps(const TbArgs &b, hipStream_t s);
+
+// The same for the lattices of a batch that use the multi-sweep traversal (one launch for
+// all of them, S odd so that the state stays in the buffer of its sweep index's parity).
+constexpr int kTbBatchSweeps = 7;  // sweeps per launch (odd)
+constexpr int kTbBatchSide = 8;    // tile side
+struct TbBatchLaunch {
+    const ImageDesc *imgs;
+    const int *block_img;  // workgroup -> lattice (each lattice's tiles consecutive from its block_base)
+    uint32_t toff;         // first sweep of the launch, relative to each lattice's sweep index
+    int S;                 // sweeps (odd), fewer for a lattice that reaches its end
+};
+size_t tb_batch_lds_bytes(int H, int W, int Cp, int side, int S, int ptab_n);
+hipError_t launch_tb_batch(const TbBatchLaunch &L, int blocks, int G, int share, int nbr, size_t lds_bytes,
+                           hipStream_t s);
 
 // Device buffers of one single-lattice run and the chain layout that goes with them.
 struct RunBuffers {

@@ -73,22 +73,25 @@ __device__ __forceinline__ int small_div(int n, int d, float inv_d)
     return q;
 }
 
-template <int G, int NBR, int SHARE, int BLK>
-__global__ __launch_bounds__(BLK) void tb_sweep_kernel(TbArgs b)
+// The sweeps of one tile: `a` holds the lattice (a.t the first sweep, a.xin / a.xout the
+// state before and after, a.sum / a.hist the accumulators), tile `tile` of a grid of
+// tiles_w tiles per row, each TH x TW; sch gives each sweep's beta and whether it adds to
+// the level sum (acc) and to the histogram (tally).
+template <int G, int NBR, int SHARE, int BLK, class Schedule>
+__device__ __forceinline__ void tb_tile(SweepArgs a, int tile, int TH, int TW, int tiles_w, int S, int ptab_n,
+                                        const Schedule &sch, unsigned char *lds)
 {
-    extern __shared__ __align__(16) unsigned char lds[];
-    SweepArgs a = b.a;
     const int tid = (int)threadIdx.x;
-    const int Cp = a.Cp, tpp = Cp / G, H = a.H, W = a.W, S = b.S;
+    const int Cp = a.Cp, tpp = Cp / G, H = a.H, W = a.W;
 
     // The tile [r0, r1) x [c0, c1) and the loaded region: the tile grown by S, clipped.
-    const int tr = (int)blockIdx.x / b.tiles_w, tc = (int)blockIdx.x - tr * b.tiles_w;
-    const int r0 = tr * b.TH, c0 = tc * b.TW;
-    const int r1 = min(H, r0 + b.TH), c1 = min(W, c0 + b.TW);
+    const int tr = tile / tiles_w, tc = tile - tr * tiles_w;
+    const int r0 = tr * TH, c0 = tc * TW;
+    const int r1 = min(H, r0 + TH), c1 = min(W, c0 + TW);
     const int gr0 = max(0, r0 - S), gc0 = max(0, c0 - S), gr1 = min(H, r1 + S), gc1 = min(W, c1 + S);
     const int w0 = gc1 - gc0, h0 = gr1 - gr0;
-    const bool sums = b.acc_mask != 0u;
-    const TbLayout lay = tb_lds_layout(w0 * h0, Cp, b.TH * b.TW, b.ptab_n, sums);
+    const bool sums = sch.any_acc();
+    const TbLayout lay = tb_lds_layout(w0 * h0, Cp, TH * TW, ptab_n, sums);
     float *ptab = reinterpret_cast<float *>(lds + lay.ptab);
     float *gpl = reinterpret_cast<float *>(lds + lay.gp);
     uint8_t *xa = lds + lay.xa;
@@ -104,23 +107,25 @@ __global__ __launch_bounds__(BLK) void tb_sweep_kernel(TbArgs b)
     copy_rows(xa, (int64_t)w0 * Cp, a.xin + ((int64_t)gr0 * W + gc0) * Cp, (int64_t)W * Cp, h0, w0 * Cp, dwords, tid,
               BLK);
     if (sums)
-        for (int i = tid; i < b.TH * b.TW; i += BLK) suml[i] = 0u;
+        for (int i = tid; i < TH * TW; i += BLK) suml[i] = 0u;
 
     const float inv_tpp = 1.0f / (float)tpp;
     const uint32_t t0 = a.t;
     SweepConsts kc{};
+    double beta_prev = 0.0;
     for (int s = 0; s < S; ++s) {
         a.t = t0 + (uint32_t)s;
-        a.beta = b.beta[s];
-        if (s == 0 || b.beta[s] != b.beta[s - 1]) {
+        a.beta = sch.beta(s);
+        if (s == 0 || a.beta != beta_prev) {
             __syncthreads();  // the previous sweep's table reads are done
             fill_prior_table(a, NBR, ptab, tid, BLK);
             kc = sweep_constants(a);
+            beta_prev = a.beta;
         }
         __syncthreads();  // table, and the state of sweep t0 + s, complete
         const uint8_t *in = (s & 1) ? xb : xa;
         uint8_t *out = (s & 1) ? xa : xb;
-        const bool acc = (b.acc_mask >> s) & 1u, tally = (b.tally_mask >> s) & 1u;
+        const bool acc = sch.acc(s), tally = sch.tally(s);
 
         // Sites of sweep s: the tile grown by e = S - 1 - s, clipped to the lattice.
         const int e = S - 1 - s;
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(BLK) void tb_sweep_kernel(TbArgs b)
             store_group<G>(out + li * Cp + grp * G, packed);
             if ((acc || tally) && r >= r0 && r < r1 && c >= c0 && c < c1) {
                 // the tile's own sites: level sums into LDS, tallies into the histogram
-                site_stats<G, 1>(acc ? suml + (r - r0) * b.TW + (c - c0) : nullptr,
+                site_stats<G, 1>(acc ? suml + (r - r0) * TW + (c - c0) : nullptr,
                                  tally ? a.hist + (int64_t)pix * a.hist_words : nullptr, a.hist_words, a.C, tpp, grp,
                                  knew);
             }
@@ -164,9 +169,86 @@ __global__ __launch_bounds__(BLK) void tb_sweep_kernel(TbArgs b)
         const int tw = c1 - c0, n = (r1 - r0) * tw;
         for (int i = tid; i < n; i += BLK) {
             const int rr = i / tw, cc = i - rr * tw;
-            a.sum[(int64_t)(r0 + rr) * W + c0 + cc] += suml[rr * b.TW + cc];
+            a.sum[(int64_t)(r0 + rr) * W + c0 + cc] += suml[rr * TW + cc];
         }
     }
+}
+
+// Schedule of a single-lattice launch: from the host-filled arguments.
+struct ArgSchedule {
+    const TbArgs &b;
+    __device__ double beta(int s) const { return b.beta[s]; }
+    __device__ bool acc(int s) const { return (b.acc_mask >> s) & 1u; }
+    __device__ bool tally(int s) const { return (b.tally_mask >> s) & 1u; }
+    __device__ bool any_acc() const { return b.acc_mask != 0u; }
+};
+
+template <int G, int NBR, int SHARE, int BLK>
+__global__ __launch_bounds__(BLK) void tb_sweep_kernel(TbArgs b)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    tb_tile<G, NBR, SHARE, BLK>(b.a, (int)blockIdx.x, b.TH, b.TW, b.tiles_w, b.S, b.ptab_n, ArgSchedule{b}, lds);
+}
+
+// Schedule of a lattice in a batched launch: from its descriptor, sweeps t0 .. t0+S-1.
+struct DescSchedule {
+    const ImageDesc &d;
+    uint32_t t0;
+    __device__ double beta(int s) const
+    {
+        const uint32_t t = t0 + (uint32_t)s;
+        return d.beta_len == 0 ? 1.0 : d.beta[t < (uint32_t)d.beta_len ? t : (uint32_t)(d.beta_len - 1)];
+    }
+    __device__ bool acc(int s) const { return (int64_t)(t0 + (uint32_t)s) >= d.burn_in; }
+    __device__ bool tally(int s) const
+    {
+        const int64_t t = (int64_t)(t0 + (uint32_t)s);
+        return t >= d.burn_in && d.tally_stride > 0 && (t - d.burn_in) % d.tally_stride == 0;
+    }
+    __device__ bool any_acc() const { return acc(S - 1); }
+    int S;
+};
+
+// Several sweeps of every lattice a batch runs from LDS tiles (the batch's "multi-sweep"
+// traversal): workgroup -> lattice by a table, each lattice's tiles consecutive.  S is odd,
+// so a lattice's state after the launch is in the buffer of its new sweep index's parity,
+// as the one-sweep launches keep it.
+template <int G, int NBR, int SHARE, int BLK>
+__global__ __launch_bounds__(BLK) void tb_batch_kernel(TbBatchLaunch L)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int img = L.block_img[blockIdx.x];
+    const ImageDesc &d = L.imgs[img];
+    const uint32_t t0 = d.t + L.toff;
+    if (t0 >= d.t_end) return;  // this lattice has finished (uniform over the workgroup)
+    const int S = (int)min((uint32_t)L.S, d.t_end - t0);
+    SweepArgs a;
+    a.gp = d.gp;
+    a.xin = (t0 & 1u) ? d.x1 : d.x0;
+    a.xout = (t0 & 1u) ? d.x0 : d.x1;
+    a.sum = d.sum;
+    a.hist = d.hist;
+    a.H = d.H;
+    a.W = d.W;
+    a.L = d.L;
+    a.C = d.C;
+    a.Cp = d.Cp;
+    a.T = d.T;
+    a.hist_words = d.hist_words;
+    a.beta = 1.0;
+    a.J = d.J;
+    a.q = d.q;
+    a.kappa = d.kappa;
+    a.sigma_s = d.sigma_s;
+    a.key0 = d.key0;
+    a.key1 = d.key1;
+    a.t = t0;
+    a.inertia = 0;
+    a.blk0 = 0;
+    a.patch = -1;
+    a.tiles_w = 0;
+    tb_tile<G, NBR, SHARE, BLK>(a, (int)blockIdx.x - d.block_base, d.tb_side, d.tb_side, d.tiles_w, S,
+                                NBR * d.T + 1, DescSchedule{d, t0, S}, lds);
 }
 
 template <int G, int NBR, int SHARE>
@@ -188,7 +270,44 @@ hipError_t launch_tb_g(const TbArgs &b, size_t lds_bytes, hipStream_t s)
     return launch_tb_gs<G, NBR, 1>(b, lds_bytes, s);
 }
 
+template <int G, int NBR, int SHARE>
+hipError_t launch_tb_batch_gs(const TbBatchLaunch &L, int blocks, size_t lds_bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL((tb_batch_kernel<G, NBR, SHARE, kTbBlock>), dim3((unsigned)blocks), dim3(kTbBlock), lds_bytes,
+                       s, L);
+    return hipGetLastError();
+}
+
+template <int G, int NBR>
+hipError_t launch_tb_batch_g(const TbBatchLaunch &L, int blocks, int share, size_t lds_bytes, hipStream_t s)
+{
+    if constexpr (G == 4) {
+        if (share == 4) return launch_tb_batch_gs<G, NBR, 4>(L, blocks, lds_bytes, s);
+        if (share == 2) return launch_tb_batch_gs<G, NBR, 2>(L, blocks, lds_bytes, s);
+    }
+    return launch_tb_batch_gs<G, NBR, 1>(L, blocks, lds_bytes, s);
+}
+
 }  // namespace
+
+size_t tb_batch_lds_bytes(int H, int W, int Cp, int side, int S, int ptab_n)
+{
+    const int rh = std::min(H, side + 2 * S), rw = std::min(W, side + 2 * S);
+    return (size_t)tb_lds_layout(rh * rw, Cp, side * side, ptab_n, true).bytes;
+}
+
+hipError_t launch_tb_batch(const TbBatchLaunch &L, int blocks, int G, int share, int nbr, size_t lds_bytes,
+                           hipStream_t s)
+{
+    if (nbr == 8) {
+        if (G == 4) return launch_tb_batch_g<4, 8>(L, blocks, share, lds_bytes, s);
+        if (G == 2) return launch_tb_batch_g<2, 8>(L, blocks, share, lds_bytes, s);
+        return launch_tb_batch_g<1, 8>(L, blocks, share, lds_bytes, s);
+    }
+    if (G == 4) return launch_tb_batch_g<4, 4>(L, blocks, share, lds_bytes, s);
+    if (G == 2) return launch_tb_batch_g<2, 4>(L, blocks, share, lds_bytes, s);
+    return launch_tb_batch_g<1, 4>(L, blocks, share, lds_bytes, s);
+}
 
 TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia)
 {

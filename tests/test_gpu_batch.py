@@ -46,7 +46,7 @@ MIXED_CHAINS = [(30, 31, 16, 1, 11), (22, 40, 256, 2, 12), (19, 19, 2, 3, 13), (
 
 
 @pytest.mark.parametrize("config", [(4, 1, 0), (4, 1, 1), (2, 2, 0), (2, 1, 1), (1, 4, 0), (1, 4, 1), (1, 2, 0),
-                                    (1, 1, 1)])
+                                    (1, 1, 1), (4, 1, 2), (2, 2, 2), (1, 4, 2), (1, 1, 2)])
 def test_batch_matches_lattices_run_alone(config):
     problems = [_problem(*spec[:4], seed=spec[4]) for spec in MIXED]
     b = _batch(problems)
@@ -203,3 +203,26 @@ def test_batch_patches_with_many_threads_per_pixel(orc):
         assert np.array_equal(b.state(i).cpu().numpy(), ref.state), i
         assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean()), i
         assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map()), i
+
+
+
+@pytest.mark.parametrize("calls", [(4, 4, 9), (150,), (1, 2, 64)])
+def test_batch_of_small_lattices_several_sweeps_per_launch(orc, calls):
+    """Traversal 2 with only lattices of at most 16 levels: every launch advances all of them
+    by an odd number of sweeps (7, or the rest split into odd parts) from LDS tiles, and no
+    one-sweep launch remains.  Sweep counts per call give chunks 3+1, 7s+1, 1, 1+1, 7s+1;
+    every lattice equals the oracle's run (state, mean, mode)."""
+    problems = [_problem(40, 33, 16, 4, 51), _problem(64, 64, 2, 4, 52), _problem(1, 30, 5, 4, 53),
+                _problem(17, 9, 16, 8, 54, beta=[0.7 + 0.1 * i for i in range(10)])]
+    b = _batch(problems)
+    b.set_config(4, 1, 2)
+    assert b.config == (4, 1, 2)
+    for n in calls:
+        b.sweep(n)
+    total = sum(calls)
+    for i, (obs, kw) in enumerate(problems):
+        ref = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(total)
+        assert np.array_equal(b.state(i).cpu().numpy(), ref.state), (calls, i)
+        assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean()), (calls, i)
+        assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map()), (calls, i)
+    b.close()

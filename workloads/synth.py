@@ -161,10 +161,10 @@ _FAMILY = {2: (POTTS, 1, 0.8), 16: (TRUNC_LINEAR, 4, 0.4), 256: (TRUNC_LINEAR, 3
 
 
 def _mixed_request(rng: np.random.Generator, side_lo: int, side_hi: int, chains: int, sweeps: int,
-                   idx: int, name: str) -> Workload:
+                   idx: int, name: str, levels=(2, 16, 256)) -> Workload:
     H = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
     W = int(round(math.exp(rng.uniform(math.log(side_lo), math.log(side_hi)))))
-    L = int(rng.choice([2, 16, 256]))
+    L = int(rng.choice(list(levels)))
     prior, T, J0 = _FAMILY[L]
     sigma = float(rng.uniform(0.1, 0.3) * L)
     J = float(J0 * rng.uniform(0.5, 1.5))
@@ -178,10 +178,11 @@ def _mixed_request(rng: np.random.Generator, side_lo: int, side_hi: int, chains:
 
 
 def batch_mix(n_images: int = 64, *, side_lo: int = 128, side_hi: int = 1024, chains: int = 4, sweeps: int = 500,
-              seed: int = 1003) -> List[Workload]:
-    """Mixed-size batch: sides log-uniform, L in {2, 16, 256}, sigma ~ U[0.1, 0.3] L."""
+              seed: int = 1003, levels=(2, 16, 256)) -> List[Workload]:
+    """Mixed-size batch: sides log-uniform, L drawn from `levels` (default {2, 16, 256}),
+    sigma ~ U[0.1, 0.3] L."""
     rng = np.random.default_rng(seed)
-    return [_mixed_request(rng, side_lo, side_hi, chains, sweeps, i, "c4") for i in range(n_images)]
+    return [_mixed_request(rng, side_lo, side_hi, chains, sweeps, i, "c4", levels) for i in range(n_images)]
 
 
 def serving_trace(n_requests: int, *, rate: float = 50.0, side_lo: int = 64, side_hi: int = 4096, chains: int = 2,
