@@ -629,9 +629,11 @@ def main():
         timing.append((ev0, ev1))
         return s, mean, mpm
 
+    spl = 1
     for _ in range(args.warmup):
         s, _, _ = job([])
         s.sync()
+        spl = s.sweeps_per_launch()
         s.close()
     torch.cuda.synchronize()
 
@@ -648,19 +650,23 @@ def main():
         s.sync()
         s.close()
 
+    # event time over the job's sweeps per kernel launch (one launch advances spl sweeps on
+    # small lattices with few levels; the time then includes the gaps between launches)
     sweep_ms = [a.elapsed_time(b) for a, b in timing]
-    avg_launch_s = (sum(sweep_ms) / len(sweep_ms)) / 1e3 / wl.sweeps
+    launches = -(-wl.sweeps // spl)
+    per_launch = wl.sweeps / launches  # sweeps per launch, on average over the job
+    avg_launch_s = (sum(sweep_ms) / len(sweep_ms)) / 1e3 / launches
     su_total = wl.site_updates * args.steps
     value = su_total / elapsed
 
     ops_per_su = valu_ops_per_site_update(wl.levels, wl.chains, args.inertia, wl.neighbourhood)
-    launch_ops = ops_per_su * N * wl.chains
+    launch_ops = ops_per_su * N * wl.chains * per_launch
     achieved = launch_ops / avg_launch_s / 1e12
     # the committed counter summary is for the default c3 job (1000 sweeps, 250 of them burn-in)
     default_job = (args.inertia == 0 and wl.name == "c3" and args.sweeps is None and args.q is None
                    and args.neighbourhood is None)
     traffic = measured_traffic(N * wl.chains) if default_job else None
-    hbm_alg = hbm_bytes_per_launch(wl)
+    hbm_alg = hbm_bytes_per_launch(wl) * per_launch
     out = {
         "metric": "site-updates/s",
         "value": value,
@@ -687,7 +693,8 @@ def main():
             "unit": "TOP/s",
             "frac": achieved / PEAK_VALU_TOPS,
             "traffic": traffic,
-            "kernel": "sweep_kernel",
+            "kernel": "sweep_kernel" if spl == 1 else "tb_sweep_kernel",
+            "sweeps_per_launch": spl,
             "ops_per_site_update": ops_per_su,
             "ops_model": "dense-equivalent: every level of every chain counted as a full evaluation (levels "
                          "where no chain of a wave is near a neighbour's level, which the kernel handles with "
@@ -703,8 +710,8 @@ def main():
             "peak_GBs": PEAK_HBM_GBS,
             "frac": hbm_alg / avg_launch_s / 1e9 / PEAK_HBM_GBS,
             "model_bytes_per_site_update": model_bytes_per_site_update(wl.chains),
-            "frac_at_model_bytes": model_bytes_per_site_update(wl.chains) * N * wl.chains / avg_launch_s / 1e9
-                                   / PEAK_HBM_GBS,
+            "frac_at_model_bytes": model_bytes_per_site_update(wl.chains) * N * wl.chains * per_launch
+                                   / avg_launch_s / 1e9 / PEAK_HBM_GBS,
         },
         "level_evaluations_per_s": value * wl.levels,
     }
@@ -727,7 +734,7 @@ def main():
     issue = measured_valu_per_site_update() if same_kernel_work else None
     if issue is not None:
         # instructions the kernel issued (rocprofv3 SQ_INSTS_VALU x 64 lanes, same kernel source)
-        lane_insts = issue * N * wl.chains
+        lane_insts = issue * N * wl.chains * per_launch
         out["roofline"]["measured_issue"] = {
             "valu_instructions_per_site_update": issue,
             "achieved": lane_insts / avg_launch_s / 1e12,

@@ -93,8 +93,9 @@ int pca_init(const pca_params *params, const float *obs_dev, void *stream, pca_c
  * and writes state t+1, drawing each site from its conditional given the previous state
  * only; then adds every chain's new levels to the mean accumulator if t >= burn_in and to
  * the histogram on tally sweeps.  n = 0 is a no-op.  A sweep of more than 2^31 threads
- * (height*width*chains/4 for 3 or more chains) is enqueued as several kernel launches
- * with the same results.  Errors: PCA_EINVAL (n < 0),
+ * (height*width*chains/4 for 3 or more chains) is enqueued as several kernel launches,
+ * and on lattices with at most 16 levels too small to fill the GPU one kernel launch
+ * advances several sweeps (pca_sweeps_per_launch), all with the same results.  Errors: PCA_EINVAL (n < 0),
  * PCA_ESTATE (the uint32 sum or a uint16 histogram counter could overflow, or the sweep
  * index, a 32-bit counter word of the random stream, would pass 2^32 - 1), PCA_EDEVICE. */
 int pca_sweep(pca_ctx *ctx, int32_t n, void *stream);
@@ -125,6 +126,13 @@ int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream);
 /* Reports the sweep index, the number of samples in the mean accumulator (chains times
  * accumulated sweeps) and the number of tally sweeps.  Any pointer may be NULL. */
 int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *tallies);
+
+/* Reports in *out how many sweeps one kernel launch of pca_sweep advances: 1, or up to 10
+ * where each workgroup keeps a tile of the lattice with a halo as deep as that in LDS
+ * (lattices with at most 16 levels, the indicator inertia and fewer than 65536 threads in
+ * a single-sweep launch).  The results do not depend on it.  Errors: PCA_EINVAL (NULL
+ * context or out). */
+int pca_sweeps_per_launch(const pca_ctx *ctx, int32_t *out);
 
 /* Checkpoint of the accumulators (with pca_get_state and pca_stats, everything a run needs
  * to resume bit-exactly, since every draw is keyed by the sweep index and not by a

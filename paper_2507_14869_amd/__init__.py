@@ -12,6 +12,7 @@ from typing import Optional, Sequence
 from . import _lib
 from ._lib import (PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE, PCA_EBUSY, PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR, PcaError, make_params, pca_destroy,  # noqa
                    pca_get_state, pca_init, pca_last_error, pca_marginal_map, pca_posterior_mean, pca_set_state, pca_stats,
+                   pca_sweeps_per_launch,
                    pca_sweep, pca_sync, pca_batch_init, pca_batch_autotune, pca_batch_config, pca_batch_set_config,
                    pca_batch_sweep, pca_batch_posterior_mean, pca_batch_marginal_map, pca_batch_get_state,
                    pca_batch_stats, pca_batch_sync, pca_batch_destroy, pca_server_create, pca_server_submit,
@@ -89,6 +90,10 @@ class Sampler:
     def stats(self):
         """(sweep index, samples in the mean, tally sweeps)."""
         return pca_stats(self.ctx)
+
+    def sweeps_per_launch(self) -> int:
+        """Sweeps one kernel launch advances (1, or several from LDS tiles on small lattices)."""
+        return pca_sweeps_per_launch(self.ctx)
 
     def accumulators(self, stream=None):
         """(sum, hist): the raw accumulators as int32 [H, W] and int16 [H, W, levels] CUDA

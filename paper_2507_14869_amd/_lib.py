@@ -17,7 +17,7 @@ PCA_OK, PCA_EINVAL, PCA_ENOMEM, PCA_EDEVICE, PCA_ESTATE, PCA_EBUSY = 0, -1, -2, 
 PCA_PRIOR_POTTS, PCA_PRIOR_TRUNC_LINEAR = 0, 1
 
 EXPORTED = ("pca_init", "pca_sweep", "pca_posterior_mean", "pca_marginal_map", "pca_get_state", "pca_set_state",
-            "pca_stats", "pca_get_accumulators", "pca_set_accumulators", "pca_sync", "pca_destroy",
+            "pca_stats", "pca_sweeps_per_launch", "pca_get_accumulators", "pca_set_accumulators", "pca_sync", "pca_destroy",
             "pca_batch_init", "pca_batch_autotune", "pca_batch_config", "pca_batch_set_config", "pca_batch_sweep", "pca_batch_posterior_mean", "pca_batch_marginal_map",
             "pca_batch_get_state", "pca_batch_stats", "pca_batch_sync", "pca_batch_destroy", "pca_server_create",
             "pca_server_submit", "pca_server_step", "pca_server_completed", "pca_server_status", "pca_server_result",
@@ -66,6 +66,7 @@ def load():
         lib.pca_set_state.argtypes = [vp, vp, ctypes.c_int64, vp]
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.pca_stats.argtypes = [vp, i64p, i64p, i64p]
+        lib.pca_sweeps_per_launch.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
         lib.pca_get_accumulators.argtypes = [vp, vp, vp, vp]
         lib.pca_set_accumulators.argtypes = [vp, vp, vp, ctypes.c_int64, ctypes.c_int64, vp]
         lib.pca_sync.argtypes = [vp]
@@ -164,6 +165,12 @@ def pca_stats(ctx: int):
     s, c, t = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(load().pca_stats(ctypes.c_void_p(ctx), ctypes.byref(s), ctypes.byref(c), ctypes.byref(t)), "pca_stats")
     return s.value, c.value, t.value
+
+
+def pca_sweeps_per_launch(ctx: int) -> int:
+    n = ctypes.c_int32()
+    _check(load().pca_sweeps_per_launch(ctypes.c_void_p(ctx), ctypes.byref(n)), "pca_sweeps_per_launch")
+    return n.value
 
 
 def pca_get_accumulators(ctx: int, sum_ptr: int, hist_ptr: int = 0, stream: int = 0):

@@ -457,6 +457,17 @@ int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *talli
     return PCA_OK;
 }
 
+int pca_sweeps_per_launch(const pca_ctx *ctx, int32_t *out)
+{
+    int rc = check_ctx(ctx);
+    if (rc) return rc;
+    if (!out) return pcak::set_error(PCA_EINVAL, "out is NULL");
+    const pcak::TbPlan pl =
+        pcak::tb_plan(ctx->p.height, ctx->p.width, ctx->p.levels, ctx->Cp, ctx->p.neighbourhood, ctx->T, ctx->p.inertia);
+    *out = pl.S > 0 ? pl.S : 1;
+    return PCA_OK;
+}
+
 int pca_sync(pca_ctx *ctx)
 {
     g_err[0] = 0;

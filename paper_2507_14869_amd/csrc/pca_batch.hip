@@ -72,13 +72,16 @@ struct pca_batch {
 
 namespace {
 
-// A lattice that the multi-sweep traversal takes: few levels, the indicator inertia, and a
-// tile with its halo within the LDS limit.
-bool multi_sweep_lattice(const pca_batch *b, const pcak::ImageDesc &d)
+// Tile side of a lattice in the multi-sweep traversal with G chains per thread: 8, else 4
+// when the items of 8x8 tiles do not fit, or 0 when the traversal does not take it (more
+// levels, the L1/L2 inertia, or no tile fits).
+int multi_sweep_side(const pca_batch *b, const pcak::ImageDesc &d, int G)
 {
-    return !b->inr && d.L <= 16 &&
-           pcak::tb_batch_lds_bytes(d.H, d.W, d.Cp, pcak::kTbBatchSide, pcak::kTbBatchSweeps, b->nbr * d.T + 1) <=
-               (size_t)pcak::kTbMaxLds;
+    if (b->inr || d.L > 16) return 0;
+    for (int side : {pcak::kTbBatchSide, 4})
+        if (pcak::tb_fits(d.H, d.W, d.Cp, G, side, pcak::kTbBatchSweeps, b->nbr * d.T + 1, pcak::kTbBatchItems))
+            return side;
+    return 0;
 }
 
 bool config_valid(const pca_batch *b, const LaunchConfig &c)
@@ -91,7 +94,7 @@ bool config_valid(const pca_batch *b, const LaunchConfig &c)
         const int tpp = d.Cp / c.G;
         if (tpp % c.share != 0) return false;
         if (c.tiled == 1 && (tpp > pcak::kBlock / pcak::kTileW)) return false;
-        any_multi = any_multi || multi_sweep_lattice(b, d);
+        any_multi = any_multi || multi_sweep_side(b, d, c.G) > 0;
     }
     return c.tiled != 2 || any_multi;  // without such a lattice it would be configuration 0
 }
@@ -124,9 +127,9 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
         pcak::ImageDesc &d = b->desc[i];
         d.tpp = d.Cp / c.G;
         d.tb_side = 0;
-        if (c.tiled == 2 && multi_sweep_lattice(b, d)) {
+        const int side = c.tiled == 2 ? multi_sweep_side(b, d, c.G) : 0;
+        if (side > 0) {
             // its own table of workgroups, one per LDS tile
-            const int side = pcak::kTbBatchSide;
             d.tb_side = side;
             d.patch = -1;
             d.tiles_w = (d.W + side - 1) / side;
@@ -138,8 +141,7 @@ int apply_config(pca_batch *b, const LaunchConfig &c, hipStream_t s)
             } catch (const std::bad_alloc &) {
                 return fail(PCA_ENOMEM, "batch: host allocation failed");
             }
-            tb_lds = std::max(tb_lds, pcak::tb_batch_lds_bytes(d.H, d.W, d.Cp, side, pcak::kTbBatchSweeps,
-                                                                b->nbr * d.T + 1));
+            tb_lds = std::max(tb_lds, pcak::tb_lds_bytes(d.H, d.W, d.Cp, side, pcak::kTbBatchSweeps, b->nbr * d.T + 1));
             continue;
         }
         d.block_base = base;
@@ -278,7 +280,7 @@ int enqueue_eager(pca_batch *b, int32_t n, hipStream_t s)
                                                               : (left & 1) ? left : left - 1;
         if (b->tb_blocks > 0) {
             pcak::TbBatchLaunch tl{b->d_desc, b->d_tb_block_img, (uint32_t)i, S};
-            const hipError_t e = pcak::launch_tb_batch(tl, b->tb_blocks, b->cfg.G, b->cfg.share, b->nbr, b->tb_lds, s);
+            const hipError_t e = pcak::launch_tb_batch(tl, b->tb_blocks, b->cfg.G, b->nbr, b->tb_lds, s);
             if (e != hipSuccess) return hip_fail(e, "batch sweep");
         }
         for (int32_t j = i; j < i + S && b->total_blocks > 0; ++j) {

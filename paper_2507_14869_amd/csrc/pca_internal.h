@@ -164,7 +164,7 @@ struct TbArgs {
                       // a.t + S; a.sum / a.hist: accumulators of the sweeps the masks select
     int S;            // sweeps of this launch, 1..kTbMaxSweeps
     int nbr;          // neighbourhood, 4 or 8
-    int TH, TW;       // tile shape in pixels
+    int TH, TW;       // tile shape in pixels (square)
     int tiles_w;      // tiles per lattice row
     int tiles;        // tiles (workgroups) in all
     int ptab_n;       // prior table entries, nbr * T + 1
@@ -173,7 +173,8 @@ struct TbArgs {
 };
 
 // Launch plan of the multi-sweep kernel: S == 0 when it does not apply (L > 16, inertia
-// 1 or 2, or a tile with its halo would not fit the LDS limit).
+// 1 or 2, a lattice large enough to fill the GPU with one sweep, or no tile whose halo
+// and items fit).
 struct TbPlan {
     int TH, TW, S, tiles_w, tiles;
 };
@@ -181,19 +182,24 @@ struct TbPlan {
 TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia);
 hipError_t launch_tb_sweeps(const TbArgs &b, hipStream_t s);
 
+// Whether square tiles of `side` advancing S sweeps per launch fit an H x W lattice with
+// Cp chain slots, G chains per thread: the tile's own (site, chain group) items one per
+// thread, the items of the first sweep `imax` per thread, and the LDS limit.
+bool tb_fits(int H, int W, int Cp, int G, int side, int S, int ptab_n, int imax);
+size_t tb_lds_bytes(int H, int W, int Cp, int side, int S, int ptab_n);
+
 // The same for the lattices of a batch that use the multi-sweep traversal (one launch for
 // all of them, S odd so that the state stays in the buffer of its sweep index's parity).
 constexpr int kTbBatchSweeps = 7;  // sweeps per launch (odd)
-constexpr int kTbBatchSide = 8;    // tile side
+constexpr int kTbBatchSide = 8;    // tile side (4 where the items of 8x8 tiles do not fit)
+constexpr int kTbBatchItems = 4;   // items of the first sweep per thread, at most
 struct TbBatchLaunch {
     const ImageDesc *imgs;
     const int *block_img;  // workgroup -> lattice (each lattice's tiles consecutive from its block_base)
     uint32_t toff;         // first sweep of the launch, relative to each lattice's sweep index
     int S;                 // sweeps (odd), fewer for a lattice that reaches its end
 };
-size_t tb_batch_lds_bytes(int H, int W, int Cp, int side, int S, int ptab_n);
-hipError_t launch_tb_batch(const TbBatchLaunch &L, int blocks, int G, int share, int nbr, size_t lds_bytes,
-                           hipStream_t s);
+hipError_t launch_tb_batch(const TbBatchLaunch &L, int blocks, int G, int nbr, size_t lds_bytes, hipStream_t s);
 
 // Device buffers of one single-lattice run and the chain layout that goes with them.
 struct RunBuffers {

@@ -48,7 +48,8 @@ def test_null_context_is_rejected(lib):
     from paper_2507_14869_amd import _lib
     for call in (lambda: _lib.pca_sweep(None, 1), lambda: _lib.pca_posterior_mean(None, 0),
                  lambda: _lib.pca_marginal_map(None, 0), lambda: _lib.pca_get_state(None, 0),
-                 lambda: _lib.pca_set_state(None, 0, 0), lambda: _lib.pca_stats(None), lambda: _lib.pca_sync(None)):
+                 lambda: _lib.pca_set_state(None, 0, 0), lambda: _lib.pca_stats(None), lambda: _lib.pca_sync(None),
+                 lambda: _lib.pca_sweeps_per_launch(None)):
         with pytest.raises(_lib.PcaError) as e:
             call()
         assert e.value.code == _lib.PCA_EINVAL

@@ -2,9 +2,10 @@
 workgroup advances an LDS tile with a halo as deep as the sweeps it runs) against the CPU
 oracle.  The runs cross every boundary inside a launch: the beta schedule changes at
 every sweep for the first twelve (the prior table is rebuilt inside a launch), burn-in ends
-and tally sweeps fall in the middle of one, and 21 sweeps split into launches of 8, 8 and 5.
-Lattice shapes give ragged edge tiles, 1x1 and one-row lattices, and chain counts whose
-pixels take 1, 2 or 3 threads (3: no lane sharing, LDS and global atomics for the tallies).
+and tally sweeps fall in the middle of one, and 21 sweeps split into launches of 8 or fewer.
+Lattice shapes give ragged edge tiles, 1x1 and one-row lattices, tiles of 4x4, 8x8 and
+16x16 sites, level counts that are and are not powers of two, and chain counts whose
+pixels take 1, 2, 3, 4 or 8 threads (3 and 8: global atomics for the statistics).
 States, posterior means and marginal modes must be identical."""
 import numpy as np
 import pytest
@@ -24,7 +25,10 @@ pytestmark = pytest.mark.gpu
     (64, 64, 2, 1, 4, 0, 1),     # the binary workload's shape
     (17, 70, 16, 8, 8, 1, 4),
     (40, 40, 9, 2, 4, 0, 1),
-    (128, 128, 16, 4, 4, 1, 4),  # 16x16 tiles
+    (128, 128, 16, 4, 4, 1, 4),  # 8x8 tiles
+    (20, 24, 3, 16, 4, 1, 2),    # 4 threads per pixel: 4 sweeps per launch fit, not 8
+    (12, 10, 6, 29, 8, 1, 3),    # 8 threads per pixel: global atomics for the statistics
+    (240, 256, 3, 1, 4, 1, 2),   # 16x16 tiles, 4 items per thread in the first sweep
 ])
 def test_several_sweeps_per_launch_match_the_oracle(orc, case):
     torch_cuda()
