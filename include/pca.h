@@ -127,7 +127,7 @@ int pca_set_state(pca_ctx *ctx, const uint8_t *in_dev, int64_t t, void *stream);
  * accumulated sweeps) and the number of tally sweeps.  Any pointer may be NULL. */
 int pca_stats(const pca_ctx *ctx, int64_t *sweep, int64_t *count, int64_t *tallies);
 
-/* Reports in *out how many sweeps one kernel launch of pca_sweep advances: 1, or up to 10
+/* Reports in *out how many sweeps one kernel launch of pca_sweep advances: 1, or up to 12
  * where each workgroup keeps a tile of the lattice with a halo as deep as that in LDS
  * (lattices with at most 16 levels, the indicator inertia and fewer than 65536 threads in
  * a single-sweep launch).  The results do not depend on it.  Errors: PCA_EINVAL (NULL

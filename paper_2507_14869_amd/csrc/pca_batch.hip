@@ -79,7 +79,8 @@ int multi_sweep_side(const pca_batch *b, const pcak::ImageDesc &d, int G)
 {
     if (b->inr || d.L > 16) return 0;
     for (int side : {pcak::kTbBatchSide, 4})
-        if (pcak::tb_fits(d.H, d.W, d.Cp, G, side, pcak::kTbBatchSweeps, b->nbr * d.T + 1, pcak::kTbBatchItems))
+        if (pcak::tb_fits(d.H, d.W, d.Cp, G, side, pcak::kTbBatchSweeps, b->nbr * d.T + 1, pcak::kTbBatchItems,
+                          pcak::kTbBatchBlock))
             return side;
     return 0;
 }

@@ -155,7 +155,8 @@ hipError_t launch_batch_sweep_inertia(const BatchLaunch &b, int blocks, int G, i
 // workgroup advances one tile of the lattice S sweeps from an LDS copy of the tile and a
 // halo S sites deep.
 constexpr int kTbMaxSweeps = 16;
-constexpr int kTbBlock = 256;          // threads per workgroup
+constexpr int kTbBlock = 512;          // threads per workgroup (two waves per SIMD)
+constexpr int kTbItems = 2;            // items of the first sweep per thread, at most
 constexpr int kTbMaxLds = 64 * 1024;  // LDS bytes a workgroup may use
 constexpr int64_t kTbMaxThreads = 256 * 4 * 64;  // single-sweep threads below which it is used
 
@@ -183,9 +184,10 @@ TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia);
 hipError_t launch_tb_sweeps(const TbArgs &b, hipStream_t s);
 
 // Whether square tiles of `side` advancing S sweeps per launch fit an H x W lattice with
-// Cp chain slots, G chains per thread: the tile's own (site, chain group) items one per
-// thread, the items of the first sweep `imax` per thread, and the LDS limit.
-bool tb_fits(int H, int W, int Cp, int G, int side, int S, int ptab_n, int imax);
+// Cp chain slots, G chains per thread, in workgroups of `block` threads: the tile's own
+// (site, chain group) items one per thread, the items of the first sweep `imax` per
+// thread, and the LDS limit.
+bool tb_fits(int H, int W, int Cp, int G, int side, int S, int ptab_n, int imax, int block);
 size_t tb_lds_bytes(int H, int W, int Cp, int side, int S, int ptab_n);
 
 // The same for the lattices of a batch that use the multi-sweep traversal (one launch for
@@ -193,6 +195,7 @@ size_t tb_lds_bytes(int H, int W, int Cp, int side, int S, int ptab_n);
 constexpr int kTbBatchSweeps = 7;  // sweeps per launch (odd)
 constexpr int kTbBatchSide = 8;    // tile side (4 where the items of 8x8 tiles do not fit)
 constexpr int kTbBatchItems = 4;   // items of the first sweep per thread, at most
+constexpr int kTbBatchBlock = 256; // threads per workgroup
 struct TbBatchLaunch {
     const ImageDesc *imgs;
     const int *block_img;  // workgroup -> lattice (each lattice's tiles consecutive from its block_base)

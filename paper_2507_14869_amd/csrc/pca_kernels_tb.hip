@@ -13,7 +13,7 @@
 //
 // What it saves on such lattices, where a sweep is short: S - 1 of every S kernel
 // launches and the state's trips through memory between them.  A sweep here costs about
-// one site's latency (a workgroup has one wave per SIMD), so the per-site code is laid out
+// one site's latency (a workgroup has two waves per SIMD), so the per-site code is laid out
 // for a short dependent chain: every thread owns the same sites for the whole launch,
 // with their LDS addresses, neighbour presence and data factors (which depend on neither
 // the state nor beta) computed once; the level loop runs to a compile-time bound with no
@@ -592,32 +592,29 @@ __global__ __launch_bounds__(BLK) void tb_batch_kernel(TbBatchLaunch L)
 }
 
 template <int G, int NBR, int LB>
-hipError_t launch_tb_l(const TbArgs &b, int imax, size_t lds_bytes, hipStream_t s)
+hipError_t launch_tb_l(const TbArgs &b, size_t lds_bytes, hipStream_t s)
 {
-    if (imax <= 2)
-        hipLaunchKernelGGL((tb_sweep_kernel<G, NBR, LB, 2, kTbBlock>), dim3((unsigned)b.tiles), dim3(kTbBlock),
-                           lds_bytes, s, b);
-    else
-        hipLaunchKernelGGL((tb_sweep_kernel<G, NBR, LB, 4, kTbBlock>), dim3((unsigned)b.tiles), dim3(kTbBlock),
-                           lds_bytes, s, b);
+    hipLaunchKernelGGL((tb_sweep_kernel<G, NBR, LB, kTbItems, kTbBlock>), dim3((unsigned)b.tiles), dim3(kTbBlock),
+                       lds_bytes, s, b);
     return hipGetLastError();
 }
 
 template <int G, int NBR>
-hipError_t launch_tb_g(const TbArgs &b, int imax, size_t lds_bytes, hipStream_t s)
+hipError_t launch_tb_g(const TbArgs &b, size_t lds_bytes, hipStream_t s)
 {
     switch (tb_levels(b.a.L)) {
-    case 2: return launch_tb_l<G, NBR, 2>(b, imax, lds_bytes, s);
-    case 4: return launch_tb_l<G, NBR, 4>(b, imax, lds_bytes, s);
-    case 8: return launch_tb_l<G, NBR, 8>(b, imax, lds_bytes, s);
-    default: return launch_tb_l<G, NBR, 16>(b, imax, lds_bytes, s);
+    case 2: return launch_tb_l<G, NBR, 2>(b, lds_bytes, s);
+    case 4: return launch_tb_l<G, NBR, 4>(b, lds_bytes, s);
+    case 8: return launch_tb_l<G, NBR, 8>(b, lds_bytes, s);
+    default: return launch_tb_l<G, NBR, 16>(b, lds_bytes, s);
     }
 }
 
 template <int G, int NBR>
 hipError_t launch_tb_batch_g(const TbBatchLaunch &L, int blocks, size_t lds_bytes, hipStream_t s)
 {
-    hipLaunchKernelGGL((tb_batch_kernel<G, NBR, kTbBlock>), dim3((unsigned)blocks), dim3(kTbBlock), lds_bytes, s, L);
+    hipLaunchKernelGGL((tb_batch_kernel<G, NBR, kTbBatchBlock>), dim3((unsigned)blocks), dim3(kTbBatchBlock), lds_bytes,
+                       s, L);
     return hipGetLastError();
 }
 
@@ -627,11 +624,11 @@ int64_t tb_items(int side, int S, int tpp) { return (int64_t)(side + 2 * (S - 1)
 
 }  // namespace
 
-bool tb_fits(int H, int W, int Cp, int G, int side, int S, int ptab_n, int imax)
+bool tb_fits(int H, int W, int Cp, int G, int side, int S, int ptab_n, int imax, int block)
 {
     const int64_t tpp = Cp / G;
-    if ((int64_t)side * side * tpp > kTbBlock) return false;  // the tile's own items in slot 0
-    if (tb_items(side, S, (int)tpp) > (int64_t)imax * kTbBlock) return false;
+    if ((int64_t)side * side * tpp > block) return false;  // the tile's own items in slot 0
+    if (tb_items(side, S, (int)tpp) > (int64_t)imax * block) return false;
     return tb_lds_bytes(H, W, Cp, side, S, ptab_n) <= (size_t)kTbMaxLds;
 }
 
@@ -664,19 +661,20 @@ TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia)
     const int G = chain_group(Cp);
     if ((int64_t)H * W * (Cp / G) >= kTbMaxThreads) return pl;
     // Tiles as large as keep every compute unit busy (about one workgroup each), down to
-    // 4x4; the most sweeps per launch (10, else 8, 4 or 2) whose items fit.  Measured on
-    // 64x64, 1 chain, L = 2, 4x4 tiles (us per sweep): 6 sweeps per launch 1.33, 8 1.15,
-    // 10 1.12, 12 1.30 (where the items of the first sweep take four per thread), 14 1.34;
-    // 8x8 tiles with 8 sweeps 1.25.
+    // 4x4; the most sweeps per launch (12, else 10, 8, 4 or 2) whose items fit two per
+    // thread.  Measured on 64x64, 1 chain, L = 2, 4x4 tiles (us per sweep): 512 threads per
+    // workgroup, 10 sweeps per launch 1.03, 12 1.02, 14 1.05, 16 1.25; 256 threads, 8 sweeps
+    // 1.15, 10 1.10, 12 1.30; 1024 threads, 12 to 20 sweeps 1.11 to 1.19; 8x8 tiles with
+    // 512 threads and 10 or 12 sweeps 1.07, 1.08.
     static const int kSides[3] = {16, 8, 4};
-    static const int kSweeps[4] = {10, 8, 4, 2};
+    static const int kSweeps[5] = {12, 10, 8, 4, 2};
     for (int i = 0; i < 3; ++i) {
         const int side = kSides[i];
         const int64_t tiles = (int64_t)((H + side - 1) / side) * ((W + side - 1) / side);
         if (tiles < 240 && side > 4) continue;
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < 5; ++j) {
             const int S = kSweeps[j];
-            if (!tb_fits(H, W, Cp, G, side, S, nbr * T + 1, 4)) continue;
+            if (!tb_fits(H, W, Cp, G, side, S, nbr * T + 1, kTbItems, kTbBlock)) continue;
             pl.TH = pl.TW = side;
             pl.S = S;
             pl.tiles_w = (W + side - 1) / side;
@@ -692,16 +690,14 @@ hipError_t launch_tb_sweeps(const TbArgs &b, hipStream_t s)
 {
     const int G = chain_group(b.a.C);
     const size_t lds = tb_lds_bytes(b.a.H, b.a.W, b.a.Cp, b.TH, b.S, b.ptab_n);
-    const int64_t items = tb_items(b.TH, b.S, b.a.Cp / G);
-    const int imax = (int)((items + kTbBlock - 1) / kTbBlock);
     if (b.nbr == 8) {
-        if (G == 4) return launch_tb_g<4, 8>(b, imax, lds, s);
-        if (G == 2) return launch_tb_g<2, 8>(b, imax, lds, s);
-        return launch_tb_g<1, 8>(b, imax, lds, s);
+        if (G == 4) return launch_tb_g<4, 8>(b, lds, s);
+        if (G == 2) return launch_tb_g<2, 8>(b, lds, s);
+        return launch_tb_g<1, 8>(b, lds, s);
     }
-    if (G == 4) return launch_tb_g<4, 4>(b, imax, lds, s);
-    if (G == 2) return launch_tb_g<2, 4>(b, imax, lds, s);
-    return launch_tb_g<1, 4>(b, imax, lds, s);
+    if (G == 4) return launch_tb_g<4, 4>(b, lds, s);
+    if (G == 2) return launch_tb_g<2, 4>(b, lds, s);
+    return launch_tb_g<1, 4>(b, lds, s);
 }
 
 }  // namespace pcak

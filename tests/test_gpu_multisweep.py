@@ -50,3 +50,22 @@ def test_several_sweeps_per_launch_match_the_oracle(orc, case):
     assert np.array_equal(gpu2.posterior_mean().cpu().numpy(), ref.posterior_mean())
     gpu.close()
     gpu2.close()
+
+
+@pytest.mark.parametrize("shape,expected", [
+    # (H, W, L, chains, inertia), sweeps per launch
+    ((64, 64, 2, 1, 0), 12),      # the binary workload: 4x4 tiles, 12 sweeps
+    ((20, 24, 3, 16, 0), 4),      # 4 threads per pixel: the items of 8 or 10 sweeps do not fit
+    ((64, 64, 2, 1, 1), 1),       # L1 inertia: one sweep per launch
+    ((64, 64, 17, 1, 0), 1),      # more than 16 levels
+    ((512, 512, 16, 8, 0), 1),    # fills the GPU with one sweep
+])
+def test_sweeps_per_launch_reports_the_plan(shape, expected):
+    torch = torch_cuda()
+    from paper_2507_14869_amd import Sampler
+    H, W, L, C, inertia = shape
+    obs = torch.zeros((H, W), dtype=torch.float32, device="cuda")
+    s = Sampler(obs, levels=L, chains=C, prior=1, trunc=2, J=0.3, q=1.0, sigma=1.0, vmin=0.0, vmax=float(L - 1),
+                seed=5, inertia=inertia)
+    assert s.sweeps_per_launch() == expected
+    s.close()
