@@ -69,3 +69,40 @@ def test_sweeps_per_launch_reports_the_plan(shape, expected):
                 seed=5, inertia=inertia)
     assert s.sweeps_per_launch() == expected
     s.close()
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_small_lattices_match_the_oracle(orc, seed):
+    """Seeded random small lattices (sides 1-48, 2-16 levels, 1-24 chains, 4 or 8 neighbours,
+    either prior, a beta schedule or none, burn-in and tally stride) run in random call
+    splits: states, posterior means and marginal modes identical to the oracle's."""
+    torch_cuda()
+    rng = np.random.default_rng(7100 + seed)
+    H, W = int(rng.integers(1, 49)), int(rng.integers(1, 49))
+    L = int(rng.integers(2, 17))
+    C = int(rng.choice([1, 2, 3, 4, 5, 8, 12, 16, 24]))
+    nbr = int(rng.choice([4, 8]))
+    prior = 0 if L == 2 else int(rng.integers(0, 2))
+    T = int(rng.integers(1, 8))
+    beta = [float(b) for b in rng.uniform(0.5, 2.0, size=int(rng.integers(0, 20)))]
+    sweeps = int(rng.integers(1, 26))
+    truth = synth.random_image(H, W, L, max(2, H * W // 200), L > 2, rng)
+    obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), float(rng.uniform(0.1, 0.3)) * L, rng)
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=nbr, prior=prior, trunc=T,
+              J=float(rng.uniform(0.05, 0.8)), q=float(rng.uniform(0.0, 2.0)), sigma=float(rng.uniform(0.1, 0.3)) * L,
+              vmin=0.0, vmax=float(L - 1), beta=beta, seed=int(rng.integers(0, 2**62)),
+              burn_in=int(rng.integers(0, sweeps)), tally_stride=int(rng.integers(0, 4)))
+    ref = oracle_run(orc, obs, **kw).sweep(sweeps)
+    gpu = gpu_sampler(obs, **kw)
+    done = 0
+    while done < sweeps:
+        n = int(rng.integers(1, sweeps - done + 1))
+        gpu.sweep(n)
+        done += n
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    if ref.count[0] > 0:
+        assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    stride, b0 = kw["tally_stride"], kw["burn_in"]
+    if stride > 0 and any(t >= b0 and (t - b0) % stride == 0 for t in range(sweeps)):
+        assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+    gpu.close()
