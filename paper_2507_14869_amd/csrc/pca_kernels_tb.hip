@@ -553,7 +553,10 @@ __global__ __launch_bounds__(BLK) void tb_batch_kernel(TbBatchLaunch L)
     const int img = L.block_img[blockIdx.x];
     const ImageDesc &d = L.imgs[img];
     const uint32_t t0 = d.t + L.toff;
-    if (t0 >= d.t_end) return;  // this lattice has finished (uniform over the workgroup)
+    // A batch's lattices run to the same sweep index (t_end is 2^32 - 1, and the host keeps
+    // t0 + S below it), so S is the launch's odd count; only the request server ends lattices
+    // early, and it does not use this traversal.
+    if (t0 >= d.t_end) return;
     const int S = (int)min((uint32_t)L.S, d.t_end - t0);
     SweepArgs a;
     a.gp = d.gp;
