@@ -154,7 +154,7 @@ hipError_t pcak::enqueue_sweeps(const pca_params &p, const float *beta, int beta
         for (int32_t i = 0; i < n;) {
             const int S = (int)std::min<int64_t>(pl.S, n - i);
             tb.S = S;
-            tb.acc_mask = tb.tally_mask = 0u;
+            tb.acc_mask = tb.tally_mask = tb.beta_mask = 0u;
             for (int j = 0; j < S; ++j) {
                 const int64_t t = t0 + i + j;
                 const bool acc = t >= p.burn_in;
@@ -162,6 +162,7 @@ hipError_t pcak::enqueue_sweeps(const pca_params &p, const float *beta, int beta
                 tb.acc_mask |= (uint32_t)acc << j;
                 tb.tally_mask |= (uint32_t)tally << j;
                 tb.beta[j] = beta_len == 0 ? 1.0 : (double)beta[t < beta_len ? t : beta_len - 1];
+                if (j > 0 && tb.beta[j] != tb.beta[j - 1]) tb.beta_mask |= 1u << j;
             }
             tb.a.t = (uint32_t)(t0 + i);
             tb.a.xin = b.x[cur];

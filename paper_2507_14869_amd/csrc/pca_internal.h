@@ -170,6 +170,7 @@ struct TbArgs {
     int tiles;        // tiles (workgroups) in all
     int ptab_n;       // prior table entries, nbr * T + 1
     uint32_t acc_mask, tally_mask;  // bit s: sweep a.t + s adds to the sum / to the histogram
+    uint32_t beta_mask;             // bit s (s >= 1): beta of sweep a.t + s differs from the one before
     double beta[kTbMaxSweeps];      // beta of sweep a.t + s
 };
 

@@ -392,15 +392,12 @@ __device__ __forceinline__ void tb_tile(SweepArgs a, int tile, int TS, int tiles
     uint32_t lsum = 0u, cnt8[4] = {0u, 0u, 0u, 0u};
     const uint32_t t0 = a.t;
     for (int s = 0; s < S; ++s) {
-        if (s > 0) {
-            const double beta = sch.beta(s);
-            if (beta != beta_prev) {
-                __syncthreads();  // the previous sweep's table reads are done
-                a.beta = beta;
-                fill_prior_table(a, NBR, ptab, tid, BLK);
-                kc = sweep_constants(a);
-                beta_prev = beta;
-            }
+        if (s > 0 && sch.beta_changes(s, beta_prev)) {
+            __syncthreads();  // the previous sweep's table reads are done
+            a.beta = sch.beta(s);
+            fill_prior_table(a, NBR, ptab, tid, BLK);
+            kc = sweep_constants(a);
+            beta_prev = a.beta;
         }
         __syncthreads();  // table, and the state of sweep t0 + s, complete
         const uint8_t *in = (s & 1) ? xb : xa;
@@ -504,6 +501,8 @@ __device__ __forceinline__ void tb_tile(SweepArgs a, int tile, int TS, int tiles
 struct ArgSchedule {
     const TbArgs &b;
     __device__ double beta(int s) const { return b.beta[s]; }
+    // (from a mask in the arguments: no per-sweep load of beta while it stays the same)
+    __device__ bool beta_changes(int s, double) const { return (b.beta_mask >> s) & 1u; }
     __device__ bool acc(int s) const { return (b.acc_mask >> s) & 1u; }
     __device__ bool tally(int s) const { return (b.tally_mask >> s) & 1u; }
     __device__ bool any_acc() const { return b.acc_mask != 0u; }
@@ -527,6 +526,7 @@ struct DescSchedule {
         const uint32_t t = t0 + (uint32_t)s;
         return d.beta_len == 0 ? 1.0 : d.beta[t < (uint32_t)d.beta_len ? t : (uint32_t)(d.beta_len - 1)];
     }
+    __device__ bool beta_changes(int s, double prev) const { return d.beta_len > 0 && beta(s) != prev; }
     __device__ bool acc(int s) const { return (int64_t)(t0 + (uint32_t)s) >= d.burn_in; }
     __device__ bool tally(int s) const
     {
