@@ -1,0 +1,51 @@
+"""Seeded random single-lattice runs against the CPU oracle: sides 1-40, 17-256 levels (the
+16-level-block kernels), 1-16 chains, 4 or 8 neighbours, either prior, the indicator or the
+L1/L2 inertia, a beta schedule or none, burn-in and tally stride, split into random calls.
+States, posterior means and marginal modes must be identical."""
+import numpy as np
+import pytest
+
+from tests.gpu_util import gpu_sampler, oracle_run, torch_cuda
+from workloads import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(seed):
+    rng = np.random.default_rng(9300 + seed)
+    H, W = int(rng.integers(1, 41)), int(rng.integers(1, 41))
+    L = int(rng.choice([17, 24, 33, 64, 100, 200, 256]))
+    C = int(rng.choice([1, 2, 3, 4, 5, 8, 12, 16]))
+    sweeps = int(rng.integers(1, 9))
+    truth = synth.random_image(H, W, L, max(2, H * W // 200), True, rng)
+    obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), float(rng.uniform(0.05, 0.3)) * L, rng)
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=int(rng.choice([4, 8])),
+              prior=int(rng.integers(0, 2)), trunc=int(rng.integers(1, 48)), J=float(rng.uniform(0.01, 0.5)),
+              q=float(rng.uniform(0.0, 2.0)), sigma=float(rng.uniform(0.05, 0.3)) * L, vmin=0.0, vmax=float(L - 1),
+              beta=[float(b) for b in rng.uniform(0.5, 2.0, size=int(rng.integers(0, 10)))],
+              seed=int(rng.integers(0, 2**62)), burn_in=int(rng.integers(0, sweeps)),
+              tally_stride=int(rng.integers(0, 3)), inertia=int(rng.choice([0, 0, 1, 2])))
+    splits = []
+    left = sweeps
+    while left > 0:
+        n = int(rng.integers(1, left + 1))
+        splits.append(n)
+        left -= n
+    return obs, kw, sweeps, splits
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_random_lattices_match_the_oracle(orc, seed):
+    torch_cuda()
+    obs, kw, sweeps, splits = _case(seed)
+    ref = oracle_run(orc, obs, **kw).sweep(sweeps)
+    gpu = gpu_sampler(obs, **kw)
+    for n in splits:
+        gpu.sweep(n)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    if ref.count[0] > 0:
+        assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    stride, b0 = kw["tally_stride"], kw["burn_in"]
+    if stride > 0 and any(t >= b0 and (t - b0) % stride == 0 for t in range(sweeps)):
+        assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+    gpu.close()
