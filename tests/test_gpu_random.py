@@ -49,3 +49,61 @@ def test_random_lattices_match_the_oracle(orc, seed):
     if stride > 0 and any(t >= b0 and (t - b0) % stride == 0 for t in range(sweeps)):
         assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
     gpu.close()
+
+
+def _batch_case(seed):
+    """A batch of 2-6 random lattices (one neighbourhood; the indicator inertia or the
+    L1/L2 norms for all), a launch configuration and a split of the sweeps."""
+    rng = np.random.default_rng(9500 + seed)
+    nbr = int(rng.choice([4, 8]))
+    norms = bool(rng.integers(0, 4) == 0)
+    problems = []
+    for _ in range(int(rng.integers(2, 7))):
+        H, W = int(rng.integers(1, 41)), int(rng.integers(1, 41))
+        L = int(rng.choice([2, 5, 16, 17, 64, 256]))
+        truth = synth.random_image(H, W, L, max(2, H * W // 200), L > 2, rng)
+        obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), float(rng.uniform(0.1, 0.3)) * L, rng)
+        kw = dict(height=H, width=W, levels=L, chains=int(rng.choice([1, 2, 3, 4, 6, 8])), neighbourhood=nbr,
+                  prior=0 if L == 2 else int(rng.integers(0, 2)), trunc=int(rng.integers(1, 40)),
+                  J=float(rng.uniform(0.01, 0.6)), q=float(rng.uniform(0.0, 2.0)),
+                  sigma=float(rng.uniform(0.1, 0.3)) * L, vmin=0.0, vmax=float(L - 1),
+                  beta=[float(b) for b in rng.uniform(0.5, 2.0, size=int(rng.integers(0, 8)))],
+                  seed=int(rng.integers(0, 2**62)), burn_in=int(rng.integers(0, 4)),
+                  tally_stride=int(rng.integers(0, 3)), inertia=int(rng.integers(1, 3)) if norms else 0)
+        problems.append((obs, kw))
+    sweeps = int(rng.integers(1, 12))
+    splits = []
+    left = sweeps
+    while left > 0:
+        n = int(rng.integers(1, left + 1))
+        splits.append(n)
+        left -= n
+    return problems, sweeps, splits, rng
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_batches_match_the_oracle(orc, seed):
+    torch = torch_cuda()
+    from paper_2507_14869_amd import Batch, PcaError
+    problems, sweeps, splits, rng = _batch_case(seed)
+    b = Batch([(torch.from_numpy(o).cuda(), {k: v for k, v in kw.items() if k not in ("height", "width")})
+               for o, kw in problems])
+    # a launch configuration drawn among the valid ones (the batch rejects the others)
+    configs = [(g, s, t) for g in (4, 2, 1) for s in (4, 2, 1) for t in (0, 1, 2)]
+    for i in rng.permutation(len(configs)):
+        try:
+            b.set_config(*configs[i])
+            break
+        except PcaError:
+            continue
+    for n in splits:
+        b.sweep(n)
+    for i, (obs, kw) in enumerate(problems):
+        ref = oracle_run(orc, obs, **kw).sweep(sweeps)
+        assert np.array_equal(b.state(i).cpu().numpy(), ref.state), (i, b.config)
+        if ref.count[0] > 0:
+            assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean()), (i, b.config)
+        stride, b0 = kw["tally_stride"], kw["burn_in"]
+        if stride > 0 and any(t >= b0 and (t - b0) % stride == 0 for t in range(sweeps)):
+            assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map()), (i, b.config)
+    b.close()
