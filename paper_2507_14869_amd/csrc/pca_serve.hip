@@ -251,6 +251,16 @@ struct StreamDrain {
     ~StreamDrain() { (void)hipStreamSynchronize(s); }
 };
 
+// Releases the staging copies of the requests a step admitted, on every return path; declared
+// before the step's StreamDrain, so it runs after the drain has waited for their uploads.
+struct StagingRelease {
+    const std::vector<Request *> &admitted;
+    ~StagingRelease()
+    {
+        for (auto *r : admitted) release_staging(r);
+    }
+};
+
 struct StepEvents {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     bool ok = false;
@@ -395,6 +405,8 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     std::vector<pcak::ImageDesc> desc;
     std::vector<int> block_img;
     std::vector<int> blocks_upto;  // blocks of the first j requests
+    std::vector<Request *> admitted;
+    const StagingRelease staging{admitted};  // runs after the drain below
     const StreamDrain drain{s};    // declared after the vectors: runs before they are freed
     // 1. admission, first come first served, by device footprint and free slots (no
     //    synchronisation here: the uploads and initialisations are stream-ordered before
@@ -402,7 +414,6 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     //    request's allocation fails while others hold device memory, it stays at the head
     //    of the queue until they finish; if it fails with nothing else admitted, waiting
     //    cannot help and the request fails.  Either way the admitted requests advance.
-    std::vector<Request *> admitted;
     while (!sv->queue.empty() && (int)sv->active.size() < sv->max_active &&
            sv->used + sv->queue.front()->footprint <= sv->budget) {
         Request *r = sv->queue.front();
@@ -518,13 +529,27 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     StepEvents ev;
     if (ev.ok) (void)hipEventRecord(ev.e0, s);
     size_t j = launched.size();
+    int enqueued = 0;  // launches enqueued (each advanced the requests it covered by one sweep)
     for (int i = 0; i < K && e == hipSuccess; ++i) {
         while (j > 0 && k[launched[j - 1]] <= i) --j;  // requests still advancing at launch i
         pcak::BatchLaunch bl{sv->d_desc, sv->d_block_img, (uint32_t)i};
         e = pcak::launch_batch_sweep(bl, blocks_upto[j - 1], G, share, 0, nbr, inr, s);
+        if (e == hipSuccess) enqueued = i + 1;
     }
     if (ev.ok) (void)hipEventRecord(ev.e1, s);
-    if (e != hipSuccess) return hip_fail(e, "server: sweep launch");
+    if (e != hipSuccess) {
+        // the sweeps enqueued before the failure still count, so each request's sweep index
+        // keeps matching its device state
+        for (auto *r : launched) {
+            const int64_t adv = std::min<int64_t>(k[r], enqueued);
+            int64_t sweeps = 0, tallies = 0;
+            pcak::accumulating_sweeps(r->t, adv, r->p.burn_in, r->p.tally_stride, &sweeps, &tallies);
+            r->count += sweeps * r->p.chains;
+            r->tallies += tallies;
+            r->t += adv;
+        }
+        return hip_fail(e, "server: sweep launch");
+    }
     sv->steps += 1;
     sv->sweeps_launched += K;
     // 3. bookkeeping of the sweeps each request took, read-out of finished requests; a
@@ -553,7 +578,6 @@ int pca_server_step(pca_server *sv, void *stream, int32_t *n_completed)
     // uploads came from host vectors local to this call
     e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "server: step");
-    for (auto *r : admitted) release_staging(r);
     if (ev.ok) {  // refine the cost model from the measured step
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev.e0, ev.e1) == hipSuccess && units > 0.0 && ms > 0.0f)
