@@ -525,11 +525,25 @@ int pca_batch_sweep(pca_batch *b, int32_t n, void *stream)
     if (full > 0 && !ex_full) return rc;
     hipGraphExec_t ex_rest = rest > 0 ? graph_for(b, rest, &rc) : nullptr;
     if (rest > 0 && !ex_rest) return rc;
+    int32_t swept = 0;  // sweeps of the graphs launched (each advances the device sweep index)
+    hipError_t e = hipSuccess;
     for (int32_t i = 0; i <= full; ++i) {
         hipGraphExec_t ex = i < full ? ex_full : ex_rest;
         if (!ex) break;
-        hipError_t e = hipGraphLaunch(ex, s);
-        if (e != hipSuccess) return hip_fail(e, "batch sweep: graph launch");
+        e = hipGraphLaunch(ex, s);
+        if (e != hipSuccess) break;
+        swept += i < full ? kGraphSweeps : rest;
+    }
+    if (swept < n) {  // a launch failed: the graphs before it still count
+        for (int i = 0; i < b->n; ++i) {
+            const pca_params &p = b->p[i];
+            int64_t sweeps = 0, tallies = 0;
+            pcak::accumulating_sweeps(b->t, swept, p.burn_in, p.tally_stride, &sweeps, &tallies);
+            b->count[i] += sweeps * p.chains;
+            b->tallies[i] += tallies;
+        }
+        b->t += swept;
+        return hip_fail(e, "batch sweep: graph launch");
     }
     b->t += n;
     for (int i = 0; i < b->n; ++i) {
