@@ -366,6 +366,52 @@ def test_full_size_c3_whole_lattice(orc):
     gpu.close()
 
 
+def test_full_size_c2_whole_lattice(orc):
+    """512x512, L = 16, 8 chains (the few-level kernel in the benchmark's configuration):
+    12 sweeps from the oracle's initial state, every site update of every sweep against the
+    oracle's (computed in row bands on the host's cores), and the accumulators of the 8
+    sweeps after burn-in (level sums, tallies, mean and mode) against those states; then one
+    sweep from an oracle-made random state at sweep 4321, checked at every site."""
+    torch = torch_cuda()
+    wl = synth.make_workload("c2")
+    kw = wl.params(burn_in=4)
+    p = orc.Params(**kw)
+    gpu = gpu_sampler(wl.obs, **kw)
+    x = orc.init_state(p, wl.obs)
+    assert np.array_equal(gpu.state().cpu().numpy(), x)
+    C, H, W, L = wl.chains, wl.height, wl.width, wl.levels
+    want_sum = np.zeros((H, W), dtype=np.uint32)
+    want_hist = np.zeros(H * W * L, dtype=np.int64)
+    cell0 = np.arange(H * W, dtype=np.int64)[None, :] * L
+    for t in range(12):
+        x = orc.pca_sweep_threaded(p, wl.obs, x, t, threads=_host_threads())
+        gpu.sweep(1)
+        bad = int((gpu.state().cpu().numpy() != x).sum())
+        assert bad == 0, f"{bad} of {x.size} site updates differ at sweep {t}"
+        if t >= 4:
+            want_sum += x.sum(axis=0, dtype=np.uint32)
+            want_hist += np.bincount((cell0 + x.reshape(C, -1)).reshape(-1), minlength=H * W * L)
+    assert gpu.stats() == (12, 8 * C, 8)
+    s, h = gpu.accumulators()
+    assert np.array_equal(s.cpu().numpy().view(np.uint32), want_sum)
+    assert np.array_equal(h.cpu().numpy().view(np.uint16), want_hist.reshape(H, W, L).astype(np.uint16))
+    ref = orc.Run(p, wl.obs)  # the oracle's read-outs of the same accumulators
+    ref.sum[...] = want_sum
+    ref.count[0] = 8 * C
+    ref.hist[...] = want_hist.reshape(H, W, L)
+    assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+
+    rng = np.random.default_rng(47)
+    start = rng.integers(0, L, size=x.shape, dtype=np.uint8)
+    gpu.set_state(torch.from_numpy(start).cuda(), 4321)
+    gpu.sweep(1)
+    want = orc.pca_sweep_threaded(p, wl.obs, start, 4321, threads=_host_threads())
+    bad = int((gpu.state().cpu().numpy() != want).sum())
+    assert bad == 0, f"{bad} of {want.size} site updates differ"
+    gpu.close()
+
+
 def test_set_state_rejects_values_outside_the_levels():
     """A state value >= levels is refused (PCA_EINVAL) and leaves the context as it was;
     levels - 1 is accepted."""
