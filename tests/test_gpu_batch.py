@@ -226,3 +226,39 @@ def test_batch_of_small_lattices_several_sweeps_per_launch(orc, calls):
         assert np.array_equal(b.posterior_mean(i).cpu().numpy(), ref.posterior_mean()), (calls, i)
         assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map()), (calls, i)
     b.close()
+
+
+def test_full_size_mixed_batch_against_the_oracle(orc):
+    """The 64-lattice mixed batch of the benchmark (sides 128-1024, L in {2, 16, 256}, 4
+    chains) at full size: two sweeps in the untiled and the tiled traversal, every site update
+    and every lattice's posterior mean against the oracle (sweeps computed in row bands on the
+    host's cores)."""
+    import os
+    torch = torch_cuda()
+    from paper_2507_14869_amd import Batch
+    wls = synth.batch_mix(64, sweeps=2)
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    problems, want_state, want_mean = [], [], []
+    for w in wls:
+        kw = w.params(burn_in=0, tally_stride=1)
+        p = orc.Params(**kw)
+        x0 = orc.init_state(p, w.obs)
+        x1 = orc.pca_sweep_threaded(p, w.obs, x0, 0, threads=threads)
+        x2 = orc.pca_sweep_threaded(p, w.obs, x1, 1, threads=threads)
+        want_state.append(x2)
+        ref = orc.Run(p, w.obs)  # the oracle's mean of the accumulated level sums
+        ref.sum[...] = x1.sum(axis=0, dtype=np.uint32) + x2.sum(axis=0, dtype=np.uint32)
+        ref.count[0] = 2 * w.chains
+        want_mean.append(ref.posterior_mean())
+        kw.pop("height")
+        kw.pop("width")
+        problems.append((torch.from_numpy(w.obs).cuda(), kw))
+    for cfg in ((4, 1, 0), (4, 1, 1)):
+        b = Batch(problems)
+        b.set_config(*cfg)
+        b.sweep(2)
+        for i in range(len(problems)):
+            bad = int((b.state(i).cpu().numpy() != want_state[i]).sum())
+            assert bad == 0, (cfg, i, bad)
+            assert np.array_equal(b.posterior_mean(i).cpu().numpy(), want_mean[i]), (cfg, i)
+        b.close()
