@@ -675,11 +675,21 @@ struct StatsPrefetch {
     bool valid;
     uint32_t sum;      // the pixel's level sum (when this lane updates it)
     uint32_t row[8];   // the lane's histogram words, indexed by word (L <= 16 row path)
+    uint4 q0, q1;      // full rows (row_in_quads): the lane's words 4 grp .. 4 grp + 3, and 4 .. 7
 };
+
+// A full histogram row (8 words: L = 15 or 16) with at most 15 chains and one or two lanes
+// per pixel: each lane then owns a contiguous, 16-byte aligned run of the row (all 8 words,
+// or words 4 grp .. 4 grp + 3) and moves it with 16-byte loads and stores instead of one
+// access per word.
+__device__ __forceinline__ bool row_in_quads(int hist_words, int C, int tpp)
+{
+    return hist_words == 8 && C <= 15 && (tpp == 1 || tpp == 2);
+}
 
 template <int G, int SUB>
 __device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hist_words, int C, int tpp, int grp,
-                                           const int (&knew)[G], const StatsPrefetch &pf = StatsPrefetch{false, 0u, {}})
+                                           const int (&knew)[G], const StatsPrefetch &pf = StatsPrefetch{false, 0u, {}, {}, {}})
 {
     const int chain0 = grp * G;
     if (sum) {
@@ -701,7 +711,40 @@ __device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hi
         }
     }
     if (hrow) {
-        if (SUB == 1 && C <= 15 && (tpp == 1 || tpp == 2 || tpp == 4)) {
+        if (SUB == 1 && row_in_quads(hist_words, C, tpp)) {
+            // 4-bit counters as below; lane grp adds levels 8 grp .. 8 grp + 7 (tpp = 2) or
+            // all 16 (tpp = 1) as uint16 pairs.
+            uint32_t n0 = 0u, n1 = 0u;
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) {
+                const uint32_t inc = chain0 + ch < C ? 1u << (4 * (knew[ch] & 7)) : 0u;
+                if (knew[ch] < 8) n0 += inc;
+                else n1 += inc;
+            }
+            auto widen = [](uint32_t b) { return (b & 0xFu) | ((b >> 4) << 16); };
+            uint32_t *q = hrow + 4 * grp;
+            if (tpp == 2) {
+                n0 += (uint32_t)__builtin_amdgcn_mov_dpp((int)n0, 0xB1, 0xF, 0xF, false);
+                n1 += (uint32_t)__builtin_amdgcn_mov_dpp((int)n1, 0xB1, 0xF, 0xF, false);
+                n0 = grp ? n1 : n0;
+            }
+            if (n0 != 0u) {
+                uint4 v = pf.valid ? pf.q0 : *reinterpret_cast<const uint4 *>(q);
+                v.x += widen(n0 & 0xFFu);
+                v.y += widen((n0 >> 8) & 0xFFu);
+                v.z += widen((n0 >> 16) & 0xFFu);
+                v.w += widen(n0 >> 24);
+                *reinterpret_cast<uint4 *>(q) = v;
+            }
+            if (tpp == 1 && n1 != 0u) {
+                uint4 v = pf.valid ? pf.q1 : *reinterpret_cast<const uint4 *>(hrow + 4);
+                v.x += widen(n1 & 0xFFu);
+                v.y += widen((n1 >> 8) & 0xFFu);
+                v.z += widen((n1 >> 16) & 0xFFu);
+                v.w += widen(n1 >> 24);
+                *reinterpret_cast<uint4 *>(hrow + 4) = v;
+            }
+        } else if (SUB == 1 && C <= 15 && (tpp == 1 || tpp == 2 || tpp == 4)) {
             // L <= 16 and at most 15 chains: a pixel's 16 counters fit one 64-bit word of
             // 4-bit counters (no count reaches 16), built by shifts, summed across the
             // pixel's lanes with DPP and widened to the uint16 row, each lane adding its
@@ -788,10 +831,14 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
     // with few levels (a short level loop), the accumulator words this lane will update
     // are loaded now (see StatsPrefetch); the 16-level-block kernels would spill them
     const int tpp = a.Cp / G;
-    StatsPrefetch pf{SUB == 1, 0u, {}};
+    StatsPrefetch pf{SUB == 1, 0u, {}, {}, {}};
     if constexpr (SUB == 1) {
         if (a.sum && (tpp == 1 || ((tpp == 2 || tpp == 4) && grp == 0))) pf.sum = a.sum[pix];
-        if (a.hist && (tpp == 1 || tpp == 2 || tpp == 4)) {
+        if (a.hist && row_in_quads(a.hist_words, a.C, tpp)) {
+            const uint32_t *hrow = a.hist + (int64_t)pix * 8;
+            pf.q0 = *reinterpret_cast<const uint4 *>(hrow + 4 * grp);
+            if (tpp == 1) pf.q1 = *reinterpret_cast<const uint4 *>(hrow + 4);
+        } else if (a.hist && (tpp == 1 || tpp == 2 || tpp == 4)) {
             const uint32_t *hrow = a.hist + (int64_t)pix * a.hist_words;
 #pragma unroll
             for (int w = 0; w < 8; ++w)
