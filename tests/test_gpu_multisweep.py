@@ -5,7 +5,8 @@ every sweep for the first twelve (the prior table is rebuilt inside a launch), b
 and tally sweeps fall in the middle of one, and 21 sweeps split into launches of 8 or fewer.
 Lattice shapes give ragged edge tiles, 1x1 and one-row lattices, tiles of 4x4, 8x8 and
 16x16 sites, level counts that are and are not powers of two, and chain counts whose
-pixels take 1, 2, 3, 4 or 8 threads (3 and 8: global atomics for the statistics).
+pixels take 1, 2, 3, 4, 8, 16 or 25 threads (3 and more than 4: global atomics for the
+statistics).
 States, posterior means and marginal modes must be identical."""
 import numpy as np
 import pytest
@@ -29,6 +30,8 @@ pytestmark = pytest.mark.gpu
     (20, 24, 3, 16, 4, 1, 2),    # 4 threads per pixel: 4 sweeps per launch fit, not 8
     (12, 10, 6, 29, 8, 1, 3),    # 8 threads per pixel: global atomics for the statistics
     (240, 256, 3, 1, 4, 1, 2),   # 16x16 tiles, 4 items per thread in the first sweep
+    (9, 11, 8, 64, 4, 1, 2),     # 16 threads per pixel, 2 sweeps per launch
+    (6, 7, 16, 100, 8, 1, 4),    # 25 threads per pixel: a pixel's threads span two waves
 ])
 def test_several_sweeps_per_launch_match_the_oracle(orc, case):
     torch_cuda()
@@ -40,7 +43,9 @@ def test_several_sweeps_per_launch_match_the_oracle(orc, case):
               sigma=0.25 * L, vmin=0.0, vmax=float(L - 1), beta=[0.8 + 0.1 * i for i in range(12)],
               seed=900 + H + W, burn_in=3, tally_stride=2)
     ref = oracle_run(orc, obs, **kw).sweep(21)
-    gpu = gpu_sampler(obs, **kw).sweep(21)
+    gpu = gpu_sampler(obs, **kw)
+    assert gpu.sweeps_per_launch() > 1
+    gpu.sweep(21)
     assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
     assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
     assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
