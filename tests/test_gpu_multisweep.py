@@ -76,7 +76,7 @@ def test_sweeps_per_launch_reports_the_plan(shape, expected):
     s.close()
 
 
-@pytest.mark.parametrize("seed", range(24))
+@pytest.mark.parametrize("seed", range(64))
 def test_random_small_lattices_match_the_oracle(orc, seed):
     """Seeded random small lattices (sides 1-48, 2-16 levels, 1-24 chains, 4 or 8 neighbours,
     either prior, a beta schedule or none, burn-in and tally stride) run in random call

@@ -1,7 +1,8 @@
 """Seeded random single-lattice runs against the CPU oracle: sides 1-40, 17-256 levels (the
 16-level-block kernels), 1-16 chains, 4 or 8 neighbours, either prior, the indicator or the
-L1/L2 inertia, a beta schedule or none, burn-in and tally stride, split into random calls.
-States, posterior means and marginal modes must be identical."""
+L1/L2 inertia, a beta schedule or none, burn-in and tally stride, split into random calls;
+random batches; and larger random lattices with at most 16 levels (the one-sweep few-level
+kernel).  States, posterior means and marginal modes must be identical."""
 import numpy as np
 import pytest
 
@@ -34,7 +35,7 @@ def _case(seed):
     return obs, kw, sweeps, splits
 
 
-@pytest.mark.parametrize("seed", range(20))
+@pytest.mark.parametrize("seed", range(48))
 def test_random_lattices_match_the_oracle(orc, seed):
     torch_cuda()
     obs, kw, sweeps, splits = _case(seed)
@@ -81,7 +82,7 @@ def _batch_case(seed):
     return problems, sweeps, splits, rng
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(30))
 def test_random_batches_match_the_oracle(orc, seed):
     torch = torch_cuda()
     from paper_2507_14869_amd import Batch, PcaError
@@ -107,3 +108,41 @@ def test_random_batches_match_the_oracle(orc, seed):
         if stride > 0 and any(t >= b0 and (t - b0) % stride == 0 for t in range(sweeps)):
             assert np.array_equal(b.marginal_map(i).cpu().numpy(), ref.marginal_map()), (i, b.config)
     b.close()
+
+
+def _few_level_case(seed):
+    """A lattice with at most 16 levels large enough (at least 256 x 256) for one sweep per
+    launch, so the one-sweep few-level kernel runs rather than the several-sweeps one."""
+    rng = np.random.default_rng(9700 + seed)
+    H, W = int(rng.integers(256, 321)), int(rng.integers(256, 321))
+    L = int(rng.integers(2, 17))
+    C = int(rng.choice([1, 2, 3, 4, 6, 8, 13, 16]))
+    sweeps = int(rng.integers(1, 4 if C <= 8 else 3))
+    truth = synth.random_image(H, W, L, int(rng.integers(5, 40)), L > 2, rng)
+    obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), float(rng.uniform(0.1, 0.3)) * L, rng)
+    kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=int(rng.choice([4, 8])),
+              prior=0 if L == 2 else int(rng.integers(0, 2)), trunc=int(rng.integers(1, 8)),
+              J=float(rng.uniform(0.05, 0.8)), q=float(rng.uniform(0.0, 2.0)), sigma=float(rng.uniform(0.1, 0.3)) * L,
+              vmin=0.0, vmax=float(L - 1), beta=[float(b) for b in rng.uniform(0.5, 2.0, size=int(rng.integers(0, 4)))],
+              seed=int(rng.integers(0, 2**62)), burn_in=int(rng.integers(0, sweeps)), tally_stride=int(rng.integers(0, 3)))
+    return obs, kw, sweeps
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_few_level_lattices_one_sweep_per_launch(orc, seed):
+    """Seeded random lattices of 256-320 sites a side with 2-16 levels and 1-16 chains (every
+    lanes-per-pixel layout of the few-level kernel's statistics), either neighbourhood and
+    prior: states, posterior means and marginal modes identical to the oracle's."""
+    torch_cuda()
+    obs, kw, sweeps = _few_level_case(seed)
+    ref = oracle_run(orc, obs, **kw).sweep(sweeps)
+    gpu = gpu_sampler(obs, **kw)
+    assert gpu.sweeps_per_launch() == 1
+    gpu.sweep(sweeps)
+    assert np.array_equal(gpu.state().cpu().numpy(), ref.state)
+    if ref.count[0] > 0:
+        assert np.array_equal(gpu.posterior_mean().cpu().numpy(), ref.posterior_mean())
+    stride, b0 = kw["tally_stride"], kw["burn_in"]
+    if stride > 0 and any(t >= b0 and (t - b0) % stride == 0 for t in range(sweeps)):
+        assert np.array_equal(gpu.marginal_map().cpu().numpy(), ref.marginal_map())
+    gpu.close()
