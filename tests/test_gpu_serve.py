@@ -11,6 +11,7 @@ except ImportError:  # pragma: no cover
 
 from tests.gpu_util import gpu_sampler, oracle_run, torch_cuda
 from tests.test_gpu_batch import _problem
+from workloads import synth
 
 pytestmark = pytest.mark.gpu
 
@@ -266,4 +267,60 @@ def test_failed_read_out_ends_the_request_without_an_extra_sweep(monkeypatch):
     ref = _alone(*probs[1], 7)
     assert np.array_equal(mean, ref[0]) and np.array_equal(mpm, ref[1]) and np.array_equal(state, ref[2])
     assert sv.stats()[:3] == (0, 0, 0)
+    sv.close()
+
+
+def _random_requests(rng):
+    reqs = []
+    for _ in range(int(rng.integers(3, 9))):
+        H, W = int(rng.integers(4, 81)), int(rng.integers(4, 81))
+        L = int(rng.choice([2, 5, 16, 33, 256]))
+        sweeps = int(rng.integers(1, 26))
+        truth = synth.random_image(H, W, L, max(2, H * W // 300), L > 2, rng)
+        sigma = float(rng.uniform(0.1, 0.3) * L)
+        obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), sigma, rng)
+        kw = dict(levels=L, chains=int(rng.integers(1, 5)), neighbourhood=int(rng.choice([4, 8])),
+                  prior=0 if L == 2 else int(rng.integers(0, 2)), trunc=int(rng.integers(1, 40)),
+                  J=float(rng.uniform(0.02, 0.8)), q=float(rng.uniform(0.0, 2.0)), sigma=sigma, vmin=0.0,
+                  vmax=float(L - 1), beta=[float(b) for b in rng.uniform(0.5, 2.0, size=int(rng.integers(0, 6)))],
+                  seed=int(rng.integers(0, 2**62)), burn_in=int(rng.integers(0, sweeps)),
+                  tally_stride=int(rng.integers(1, 3)))
+        reqs.append((obs, kw, sweeps))
+    return reqs
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_random_serving_matches_the_oracle(orc, seed):
+    """Seeded random request streams: 3-8 requests (sides 4-80, 2-256 levels, 1-4 chains,
+    either neighbourhood and prior, beta schedules, burn-in and tally stride) submitted at
+    random steps to a server with a random budget, slot count and sweeps per step; every
+    request's mean, mode and final states equal the oracle's run of it alone."""
+    rng = np.random.default_rng(6600 + seed)
+    reqs = _random_requests(rng)
+    fps = []
+    for obs, kw, _ in reqs:
+        N = obs.shape[0] * obs.shape[1]
+        C = kw["chains"]
+        Cp = C if C <= 2 else (C + 3) // 4 * 4
+        fps.append(N * (4 + 2 * Cp + 4 + 4 + ((kw["levels"] + 1) // 2) * 4) + 4096 + 24)
+    budget = max(fps) + int(rng.uniform(0.0, 1.0) * sum(fps))
+    sv = _server(budget=budget, max_active=int(rng.integers(1, 9)), k=int(rng.integers(1, 10)))
+    ids, done, nxt = {}, set(), 0
+    for _ in range(3000):
+        while nxt < len(reqs) and rng.integers(0, 3) == 0:
+            obs, kw, sweeps = reqs[nxt]
+            ids[sv.submit(obs, sweeps, **kw)] = nxt
+            nxt += 1
+        sv.step()
+        done.update(sv.completed())
+        if nxt == len(reqs) and len(done) == len(reqs):
+            break
+    assert done == set(ids)
+    for rid, i in ids.items():
+        obs, kw, sweeps = reqs[i]
+        mean, mpm, state = sv.result(rid)
+        ref = oracle_run(orc, obs, height=obs.shape[0], width=obs.shape[1], **kw).sweep(sweeps)
+        assert np.array_equal(state, ref.state), (seed, i)
+        assert np.array_equal(mean, ref.posterior_mean()), (seed, i)
+        assert np.array_equal(mpm, ref.marginal_map()), (seed, i)
     sv.close()
