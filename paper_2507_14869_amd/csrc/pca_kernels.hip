@@ -12,10 +12,11 @@ template <int G, int NBR, int SUB, int NBLK, int SHARE>
 __global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel(SweepArgs a)
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
-    const SweepConsts kc = sweep_prologue(a, NBR, ptab);
+    __shared__ uint4 vtab[kStatEntries];
+    const SweepConsts kc = sweep_prologue(a, NBR, ptab, vtab);
     int pix, r, c, grp;
     if (!sweep_thread_site(a, a.Cp / G, pix, r, c, grp)) return;
-    sweep_site<G, NBR, SUB, NBLK, SHARE>(a, ptab, kc, pix, r, c, grp, (int)(threadIdx.x % SHARE));
+    sweep_site<G, NBR, SUB, NBLK, SHARE>(a, ptab, vtab, kc, pix, r, c, grp, (int)(threadIdx.x % SHARE));
 }
 
 // ---------------------------------------------------------------- init and readouts

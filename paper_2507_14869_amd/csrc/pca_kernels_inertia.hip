@@ -11,10 +11,11 @@ template <int G, int NBR, int SUB>
 __global__ __launch_bounds__(kBlock, kMinWaves<SUB>) void sweep_kernel_inertia(SweepArgs a)
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
-    const SweepConsts kc = sweep_prologue(a, NBR, ptab);
+    __shared__ uint4 vtab[kStatEntries];
+    const SweepConsts kc = sweep_prologue(a, NBR, ptab, vtab);
     int pix, r, c, grp;
     if (!sweep_thread_site(a, a.Cp / G, pix, r, c, grp)) return;
-    sweep_site<G, NBR, SUB, 16, 1, true>(a, ptab, kc, pix, r, c, grp, 0);
+    sweep_site<G, NBR, SUB, 16, 1, true>(a, ptab, vtab, kc, pix, r, c, grp, 0);
 }
 
 template <int G, int NBR>

@@ -284,10 +284,35 @@ __device__ __forceinline__ void fill_prior_table(const SweepArgs &a, int nbr, fl
     for (int s = first; s < nP; s += stride) ptab[s] = exp2s(-(c2 * (float)s));
 }
 
-__device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nbr, float *ptab)
+// Statistic table of the few-level 4-neighbour kernels (L <= 16): entry x (a neighbour's
+// level, 0..15) holds, in byte k of its 16 bytes, 4 min(|k - x|, T), one neighbour's term of
+// the byte offset 4 S_k of P(S_k) in the prior table; entry 16 (an absent neighbour) is 0.
+// A chain's 16 offsets are then the bytewise sum of its four neighbours' entries (at most
+// 4 * 4 * 15 = 240, no carries between bytes).
+constexpr int kStatEntries = 17;
+
+__device__ __forceinline__ void fill_stat_table(const SweepArgs &a, uint32_t *vtab, int first, int stride)
+{
+    for (int i = first; i < kStatEntries * 4; i += stride) {
+        const int x = i >> 2;
+        uint32_t w = 0u;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int k = 4 * (i & 3) + b;
+            const int d = k > x ? k - x : x - k;
+            const int v = x < 16 ? 4 * (d < a.T ? d : a.T) : 0;
+            w |= (uint32_t)v << (8 * b);
+        }
+        vtab[i] = w;
+    }
+}
+
+// vtab: the statistic table, filled for the 4-neighbour few-level path (may be null).
+__device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nbr, float *ptab, uint4 *vtab = nullptr)
 {
     const SweepConsts k = sweep_constants(a);
     fill_prior_table(a, nbr, ptab, threadIdx.x, blockDim.x);
+    if (vtab && nbr == 4 && a.L <= 16) fill_stat_table(a, reinterpret_cast<uint32_t *>(vtab), threadIdx.x, blockDim.x);
     __syncthreads();
     return k;
 }
@@ -360,10 +385,13 @@ __device__ constexpr int kNbrDc[8] = {0, 0, -1, 1, -1, 1, -1, 1};
 // the new levels packed one per byte and also in knew.
 // INR selects the L1/L2 inertia form (a.inertia = 1 or 2; SHARE must then be 1).
 template <int G, int NBR, int SUB, int NBLK, int SHARE, bool INR = false>
-__device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *ptab, SweepConsts kc,
+__device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *ptab, const uint4 *vtab, SweepConsts kc,
                                               const SiteInputs<NBR> &in, int pix, int grp, int q, int (&knew)[G])
 {
     constexpr int NW = NBR / 4;
+    // the 4-neighbour few-level path (indicator inertia) reads its prior offsets from the
+    // statistic table
+    constexpr bool STAT = SUB == 1 && NBR == 4 && !INR;
     const float R = kc.R;
     const float a2 = kc.a2;
     const int cofs = grp * G;
@@ -395,7 +423,25 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
     int nlo = 1 << 20, nhi = -(1 << 20), npres = 0;
 #pragma unroll
     for (int j = 0; j < NBR; ++j) npres += present[j] ? 1 : 0;
-    if constexpr (SUB == 1) {
+    uint32_t sv[G][4];  // STAT: byte k of sv[ch][k / 4] is the offset 4 S_k of chain ch
+    if constexpr (STAT) {
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) sv[ch][d] = 0u;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t wj = present[j] ? nbw[j] : 0x10101010u;  // absent: entry 16
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) {
+                const uint4 v = vtab[(wj >> (8 * ch)) & 0xFFu];
+                sv[ch][0] += v.x;
+                sv[ch][1] += v.y;
+                sv[ch][2] += v.z;
+                sv[ch][3] += v.w;
+            }
+        }
+    } else if constexpr (SUB == 1) {
         // L <= 16, so every level and T are below 16: the four neighbours of a chain are
         // handled as the bytes of one dword (the state words transposed so that each
         // dword holds one chain's neighbours), hi = x + T needs no clamp and lo = max(x - T, 0)
@@ -457,7 +503,19 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
             // Stay weight of the lazy conditional.
             const float ex = gp - (float)xs[ch];
             const float Dx = exp2s(__builtin_fmaf(-a2, ex * ex, m));
-            const float Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)xs[ch] * 0x01010101u);
+            float Px;
+            if constexpr (STAT) {
+                const int x = xs[ch];
+                // selects of opaque values (selects of the array's elements would be folded
+                // into an indexed load, which puts the array in scratch memory)
+                uint32_t s0 = sv[ch][0], s1 = sv[ch][1], s2 = sv[ch][2], s3 = sv[ch][3];
+                asm("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3));
+                const uint32_t w01 = (x & 4) ? s1 : s0, w23 = (x & 4) ? s3 : s2;
+                const uint32_t w = (x & 8) ? w23 : w01;
+                Px = *reinterpret_cast<const float *>(pt + ((w >> (8 * (x & 3))) & 0xFFu));
+            } else {
+                Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)xs[ch] * 0x01010101u);
+            }
             stay[ch] = (Dx * Px) * R;
         }
         acc[ch] = stay[ch];
@@ -536,7 +594,16 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
                         else if (j == 1) D = group_bcast<SHARE, (SHARE > 1 ? 1 : 0)>(Dm);
                         else if (j == 2) D = group_bcast<SHARE, (SHARE > 2 ? 2 : 0)>(Dm);
                         else D = group_bcast<SHARE, (SHARE > 3 ? 3 : 0)>(Dm);
-                        level_update<G, NW, false>(pt, nb, acc, D, kk);
+                        if constexpr (STAT) {
+                            const int k = k0 + j;
+#pragma unroll
+                            for (int ch = 0; ch < G; ++ch) {
+                                const uint32_t off = (sv[ch][k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                                acc[ch] = __builtin_fmaf(D, *reinterpret_cast<const float *>(pt + off), acc[ch]);
+                            }
+                        } else {
+                            level_update<G, NW, false>(pt, nb, acc, D, kk);
+                        }
                         kk += 0x01010101u;
                     }
                     // past the last level acc stays at Z, which the draw's search relies on
@@ -814,8 +881,8 @@ __device__ __forceinline__ void site_stats(uint32_t *sum, uint32_t *hrow, int hi
 // One thread's site updates of a sweep over state in global memory: pixel (r, c) = pix,
 // chains grp*G .. grp*G+G-1 (see site_draw).
 template <int G, int NBR, int SUB, int NBLK, int SHARE, bool INR = false>
-__device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab, SweepConsts kc, int pix, int r,
-                                           int c, int grp, int q)
+__device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab, const uint4 *vtab, SweepConsts kc,
+                                           int pix, int r, int c, int grp, int q)
 {
     const int cofs = grp * G;
     SiteInputs<NBR> in;
@@ -846,7 +913,7 @@ __device__ __forceinline__ void sweep_site(const SweepArgs &a, const float *ptab
         }
     }
     int knew[G];
-    const uint32_t packed = site_draw<G, NBR, SUB, NBLK, SHARE, INR>(a, ptab, kc, in, pix, grp, q, knew);
+    const uint32_t packed = site_draw<G, NBR, SUB, NBLK, SHARE, INR>(a, ptab, vtab, kc, in, pix, grp, q, knew);
     store_group<G>(a.xout + (int64_t)pix * a.Cp + cofs, packed);
     site_stats<G, SUB>(a.sum ? a.sum + pix : nullptr, a.hist ? a.hist + (int64_t)pix * a.hist_words : nullptr,
                        a.hist_words, a.C, tpp, grp, knew, pf);
@@ -894,6 +961,7 @@ template <int G, int SHARE, int TILED, int NBR, bool INR = false>
 __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
 {
     __shared__ float ptab[kMaxNeighbourStat + 1];
+    __shared__ uint4 vtab[kStatEntries];
     const int blk = (int)blockIdx.x + b.block0;
     const int img = b.block_img[blk];
     const ImageDesc &d = b.imgs[img];
@@ -926,7 +994,7 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
     a.blk0 = 0;
     a.patch = -1;
     a.tiles_w = 0;
-    const SweepConsts kc = sweep_prologue(a, NBR, ptab);
+    const SweepConsts kc = sweep_prologue(a, NBR, ptab, vtab);
 
     const int tpp = d.tpp;
     const int local = blk - d.block_base;
@@ -951,8 +1019,8 @@ __global__ __launch_bounds__(kBlock) void batch_sweep_kernel(BatchLaunch b)
         pix = r * d.W + c;
     }
     const int q = (int)(threadIdx.x % SHARE);
-    if (a.L <= 16) sweep_site<G, NBR, 1, 16, SHARE, INR>(a, ptab, kc, pix, r, c, grp, q);
-    else sweep_site<G, NBR, 16, 16, SHARE, INR>(a, ptab, kc, pix, r, c, grp, q);
+    if (a.L <= 16) sweep_site<G, NBR, 1, 16, SHARE, INR>(a, ptab, vtab, kc, pix, r, c, grp, q);
+    else sweep_site<G, NBR, 16, 16, SHARE, INR>(a, ptab, vtab, kc, pix, r, c, grp, q);
 }
 
 // Waves per SIMD the single-lattice sweep kernels are compiled for.  With 16-level blocks
