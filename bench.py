@@ -52,6 +52,20 @@ def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0, nbr: in
     return levels * (sads + 3.0 + 15.0 / chains)
 
 
+def peak_note(wl, inertia: int, sweeps_per_launch: int) -> str:
+    """What the VALU peak is and how the kernel's instruction mix relates to the ops model
+    (the several-sweeps kernel of small lattices keeps the byte SADs)."""
+    base = ("32-bit VALU issue rate, 256 CUs x 128 lanes x 2.4 GHz (the FP32 vector peak counts an fma as "
+            "two flops); ")
+    if wl.levels <= 16 and wl.neighbourhood == 4 and inertia == 0 and sweeps_per_launch == 1:
+        return base + ("with at most 16 levels and 4 neighbours the kernel takes each (chain, level)'s "
+                       "prior-table offset from an LDS byte table (one byte extract and one fma per (chain, "
+                       "level) instead of three byte SADs, a shift-add and a 24-bit mad), so the dense-"
+                       "equivalent count is that of the SAD formulation")
+    return base + ("the kernel's integer VOP3 instructions (byte SADs, 24-bit mads, shift-adds) are 5 of its 7 "
+                   "per (chain, level)")
+
+
 def model_bytes_per_site_update(chains: int) -> float:
     """HBM bytes the method must move per site update on an accumulating sweep: state read
     and write (2 per chain), observation read (4 per pixel) and the uint32 sum
@@ -700,9 +714,7 @@ def main():
                          "where no chain of a wave is near a neighbour's level, which the kernel handles with "
                          "one fma per chain, are counted in full)",
             "avg_launch_ms": avg_launch_s * 1e3,
-            "peak_note": "32-bit VALU issue rate, 256 CUs x 128 lanes x 2.4 GHz (the FP32 vector peak counts "
-                         "an fma as two flops); the kernel's integer VOP3 instructions (byte SADs, 24-bit mads, "
-                         "shift-adds) are 5 of its 7 per (chain, level)",
+            "peak_note": peak_note(wl, args.inertia, spl),
         },
         "hbm": {
             "algorithmic_bytes_per_launch": hbm_alg,
