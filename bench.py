@@ -590,6 +590,9 @@ def main():
     ap.add_argument("--q", type=float, default=None, help="c1-c3: override the inertia weight q")
     ap.add_argument("--neighbourhood", type=int, default=None, choices=[4, 8],
                     help="c1-c3: override the neighbourhood (the paper's experiments use 8)")
+    ap.add_argument("--share", default=None, metavar="rows:N|chains:N",
+                    help="c1-c3: run one GPU's share of an N-GPU split of the workload (a strip of H/N rows, "
+                         "or C/N of the chains) on this GPU; the exchange between GPUs is not part of it")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -616,7 +619,25 @@ def main():
         bench_serve(args)
         return
 
-    wl = synth.make_workload(args.workload, sweeps=args.sweeps)
+    share = None
+    if args.share:
+        split, _, n = args.share.partition(":")
+        base = synth.make_workload(args.workload)
+        if split not in ("rows", "chains") or not n.isdigit() or int(n) < 1:
+            ap.error("--share takes rows:N or chains:N")
+        n = int(n)
+        if split == "rows" and base.height % n == 0:
+            wl = synth.make_workload(args.workload, sweeps=args.sweeps, height=base.height // n)
+        elif split == "chains" and base.chains % n == 0:
+            wl = synth.make_workload(args.workload, sweeps=args.sweeps, chains=base.chains // n)
+        else:
+            ap.error(f"--share {args.share}: N must divide the workload's {'height' if split == 'rows' else 'chains'}")
+        share = {"split": split, "of_gpus": n,
+                 "note": "one GPU's share of the workload split over that many GPUs, run alone on one GPU (a "
+                         "row strip is a separately drawn image of the strip's shape); the halo exchange of a "
+                         "row split and the final reduce of the level sums and histograms are not measured"}
+    else:
+        wl = synth.make_workload(args.workload, sweeps=args.sweeps)
     if args.q is not None:
         wl.q = args.q
     if args.neighbourhood is not None:
@@ -678,7 +699,7 @@ def main():
     achieved = launch_ops / avg_launch_s / 1e12
     # the committed counter summary is for the default c3 job (1000 sweeps, 250 of them burn-in)
     default_job = (args.inertia == 0 and wl.name == "c3" and args.sweeps is None and args.q is None
-                   and args.neighbourhood is None)
+                   and args.neighbourhood is None and args.share is None)
     traffic = measured_traffic(N * wl.chains) if default_job else None
     hbm_alg = hbm_bytes_per_launch(wl) * per_launch
     out = {
@@ -742,7 +763,8 @@ def main():
     s.close()
     out["end_to_end"] = {"ms_per_job": e2e * 1e3, "site_updates_per_s": wl.site_updates / e2e,
                          "includes": "observation upload from host memory, the job, mean and mode download"}
-    same_kernel_work = wl.name == "c3" and args.inertia == 0 and wl.neighbourhood == 4 and args.q is None
+    same_kernel_work = (wl.name == "c3" and args.inertia == 0 and wl.neighbourhood == 4 and args.q is None
+                        and args.share is None)
     issue = measured_valu_per_site_update() if same_kernel_work else None
     if issue is not None:
         # instructions the kernel issued (rocprofv3 SQ_INSTS_VALU x 64 lanes, same kernel source)
@@ -754,6 +776,8 @@ def main():
             "source": os.path.relpath(COUNTERS_FILE, ROOT),
         }
     out["quality"] = quality(wl, mean.cpu().numpy(), None if mpm is None else mpm.cpu().numpy())
+    if share:
+        out["shard"] = share
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds, args.inertia)
         if wl.name == "c1" and args.inertia == 0:
