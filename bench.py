@@ -57,10 +57,10 @@ def peak_note(wl, inertia: int, sweeps_per_launch: int) -> str:
     (the several-sweeps kernel of small lattices keeps the byte SADs)."""
     base = ("32-bit VALU issue rate, 256 CUs x 128 lanes x 2.4 GHz (the FP32 vector peak counts an fma as "
             "two flops); ")
-    if wl.levels <= 16 and wl.neighbourhood == 4 and inertia == 0 and sweeps_per_launch == 1:
-        return base + ("with at most 16 levels and 4 neighbours the kernel takes each (chain, level)'s "
-                       "prior-table offset from an LDS byte table (one byte extract and one fma per (chain, "
-                       "level) instead of three byte SADs, a shift-add and a 24-bit mad), so the dense-"
+    if wl.levels <= 16 and inertia == 0 and sweeps_per_launch == 1:
+        return base + ("with at most 16 levels the kernel takes each (chain, level)'s neighbour statistic "
+                       "from an LDS byte table (one byte extract and one fma per (chain, level) instead of "
+                       "three byte SADs per four neighbours, a shift-add and a 24-bit mad), so the dense-"
                        "equivalent count is that of the SAD formulation")
     return base + ("the kernel's integer VOP3 instructions (byte SADs, 24-bit mads, shift-adds) are 5 of its 7 "
                    "per (chain, level)")

@@ -284,15 +284,17 @@ __device__ __forceinline__ void fill_prior_table(const SweepArgs &a, int nbr, fl
     for (int s = first; s < nP; s += stride) ptab[s] = exp2s(-(c2 * (float)s));
 }
 
-// Statistic table of the few-level 4-neighbour kernels (L <= 16): entry x (a neighbour's
-// level, 0..15) holds, in byte k of its 16 bytes, 4 min(|k - x|, T), one neighbour's term of
-// the byte offset 4 S_k of P(S_k) in the prior table; entry 16 (an absent neighbour) is 0.
-// A chain's 16 offsets are then the bytewise sum of its four neighbours' entries (at most
-// 4 * 4 * 15 = 240, no carries between bytes).
+// Statistic table of the few-level kernels (L <= 16): entry x (a neighbour's level, 0..15)
+// holds, in byte k of its 16 bytes, one neighbour's term of the statistic S_k: with four
+// neighbours 4 min(|k - x|, T), its share of the byte offset 4 S_k of P(S_k) in the prior
+// table, with eight min(|k - x|, T); entry 16 (an absent neighbour) is 0.  A chain's 16
+// statistics are then the bytewise sum of its neighbours' entries (at most 4 * 4 * 15 or
+// 8 * 15, below 256: no carries between bytes).
 constexpr int kStatEntries = 17;
 
-__device__ __forceinline__ void fill_stat_table(const SweepArgs &a, uint32_t *vtab, int first, int stride)
+__device__ __forceinline__ void fill_stat_table(const SweepArgs &a, int nbr, uint32_t *vtab, int first, int stride)
 {
+    const int scale = nbr == 4 ? 4 : 1;
     for (int i = first; i < kStatEntries * 4; i += stride) {
         const int x = i >> 2;
         uint32_t w = 0u;
@@ -300,19 +302,19 @@ __device__ __forceinline__ void fill_stat_table(const SweepArgs &a, uint32_t *vt
         for (int b = 0; b < 4; ++b) {
             const int k = 4 * (i & 3) + b;
             const int d = k > x ? k - x : x - k;
-            const int v = x < 16 ? 4 * (d < a.T ? d : a.T) : 0;
+            const int v = x < 16 ? scale * (d < a.T ? d : a.T) : 0;
             w |= (uint32_t)v << (8 * b);
         }
         vtab[i] = w;
     }
 }
 
-// vtab: the statistic table, filled for the 4-neighbour few-level path (may be null).
+// vtab: the statistic table, filled for the few-level path (may be null).
 __device__ __forceinline__ SweepConsts sweep_prologue(const SweepArgs &a, int nbr, float *ptab, uint4 *vtab = nullptr)
 {
     const SweepConsts k = sweep_constants(a);
     fill_prior_table(a, nbr, ptab, threadIdx.x, blockDim.x);
-    if (vtab && nbr == 4 && a.L <= 16) fill_stat_table(a, reinterpret_cast<uint32_t *>(vtab), threadIdx.x, blockDim.x);
+    if (vtab && a.L <= 16) fill_stat_table(a, nbr, reinterpret_cast<uint32_t *>(vtab), threadIdx.x, blockDim.x);
     __syncthreads();
     return k;
 }
@@ -389,9 +391,10 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
                                               const SiteInputs<NBR> &in, int pix, int grp, int q, int (&knew)[G])
 {
     constexpr int NW = NBR / 4;
-    // the 4-neighbour few-level path (indicator inertia) reads its prior offsets from the
-    // statistic table
-    constexpr bool STAT = SUB == 1 && NBR == 4 && !INR;
+    // the few-level path (indicator inertia) reads its neighbour statistics from the
+    // statistic table; byte k of a chain's sum is 4 S_k (4 neighbours) or S_k (8)
+    constexpr bool STAT = SUB == 1 && !INR;
+    constexpr int kOffShift = NBR == 4 ? 0 : 2;
     const float R = kc.R;
     const float a2 = kc.a2;
     const int cofs = grp * G;
@@ -423,14 +426,14 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
     int nlo = 1 << 20, nhi = -(1 << 20), npres = 0;
 #pragma unroll
     for (int j = 0; j < NBR; ++j) npres += present[j] ? 1 : 0;
-    uint32_t sv[G][4];  // STAT: byte k of sv[ch][k / 4] is the offset 4 S_k of chain ch
+    uint32_t sv[G][4];  // STAT: byte k of sv[ch][k / 4] is S_k of chain ch, times 4 with 4 neighbours
     if constexpr (STAT) {
 #pragma unroll
         for (int ch = 0; ch < G; ++ch)
 #pragma unroll
             for (int d = 0; d < 4; ++d) sv[ch][d] = 0u;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < NBR; ++j) {
             const uint32_t wj = present[j] ? nbw[j] : 0x10101010u;  // absent: entry 16
 #pragma unroll
             for (int ch = 0; ch < G; ++ch) {
@@ -512,7 +515,7 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
                 asm("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3));
                 const uint32_t w01 = (x & 4) ? s1 : s0, w23 = (x & 4) ? s3 : s2;
                 const uint32_t w = (x & 8) ? w23 : w01;
-                Px = *reinterpret_cast<const float *>(pt + ((w >> (8 * (x & 3))) & 0xFFu));
+                Px = *reinterpret_cast<const float *>(pt + (((w >> (8 * (x & 3))) & 0xFFu) << kOffShift));
             } else {
                 Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)xs[ch] * 0x01010101u);
             }
@@ -598,7 +601,7 @@ __device__ __forceinline__ uint32_t site_draw(const SweepArgs &a, const float *p
                             const int k = k0 + j;
 #pragma unroll
                             for (int ch = 0; ch < G; ++ch) {
-                                const uint32_t off = (sv[ch][k >> 2] >> (8 * (k & 3))) & 0xFFu;
+                                const uint32_t off = ((sv[ch][k >> 2] >> (8 * (k & 3))) & 0xFFu) << kOffShift;
                                 acc[ch] = __builtin_fmaf(D, *reinterpret_cast<const float *>(pt + off), acc[ch]);
                             }
                         } else {
