@@ -656,13 +656,17 @@ TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia)
 {
     TbPlan pl{};
     if (L > 16 || inertia != 0) return pl;
-    // Only lattices whose single-sweep launch has fewer threads than the GPU has lanes
-    // (256 CUs x 4 SIMDs x 64): there a sweep costs a launch and one site's latency, which
-    // several sweeps per launch amortise.  On larger ones the halo's extra work and the
-    // barriers cost more than they save (measured on 512x512, L = 16, 8 chains: 23.7
-    // against 19.3 us per sweep).
+    // Only lattices whose single-sweep launch has at most as many threads as the GPU has
+    // lanes (256 CUs x 4 SIMDs x 64): there a sweep costs a launch and one site's latency,
+    // which several sweeps per launch amortise (256 x 256, one chain, 5 levels, 8 neighbours:
+    // 2.05 against 4.47 us per sweep; 4 chains, 16 levels: 5.16 against 5.73).  On larger
+    // ones the halo's extra work and the barriers cost about as much as they save or more
+    // (us per sweep, several against one sweep per launch: 256 x 256, 8 chains, 16 levels
+    // 6.99 / 6.78; 512 x 512, one chain, 9 levels, 8 neighbours 7.59 / 7.19; 512 x 512,
+    // 8 chains, 16 levels 23.7 / 19.3; but 384 x 384, one chain, 16 levels 5.05 / 5.99 and
+    // 512 x 512, one chain, 2 levels 3.44 / 5.40).
     const int G = chain_group(Cp);
-    if ((int64_t)H * W * (Cp / G) >= kTbMaxThreads) return pl;
+    if ((int64_t)H * W * (Cp / G) > kTbMaxThreads) return pl;
     // Tiles as large as keep every compute unit busy (about one workgroup each), down to
     // 4x4; the most sweeps per launch (12, else 10, 8, 4 or 2) whose items fit two per
     // thread.  Measured on 64x64, 1 chain, L = 2, 4x4 tiles (us per sweep): 512 threads per

@@ -413,13 +413,13 @@ def test_full_size_c2_whole_lattice(orc):
 
 
 @pytest.mark.parametrize("H,W,L,C,nbr", [
-    (128, 128, 16, 16, 4),  # 4 lanes per pixel, more than 15 chains: the row built as uint16 pairs
-    (128, 128, 16, 14, 4),  # 4 lanes per pixel, 4-bit counters, a padded chain group
-    (256, 256, 16, 3, 4),   # one lane per pixel owning the whole row
+    (136, 128, 16, 16, 4),  # 4 lanes per pixel, more than 15 chains: the row built as uint16 pairs
+    (136, 128, 16, 14, 4),  # 4 lanes per pixel, 4-bit counters, a padded chain group
+    (264, 256, 16, 3, 4),   # one lane per pixel owning the whole row
     (256, 256, 15, 8, 4),   # 2 lanes per pixel, 15 levels (a full row of 8 words)
-    (256, 128, 7, 8, 4),    # rows of 4 words
-    (128, 128, 2, 16, 4),   # rows of one word
-    (256, 256, 12, 2, 4),   # two chains, rows of 6 words
+    (256, 136, 7, 8, 4),    # rows of 4 words
+    (136, 128, 2, 16, 4),   # rows of one word
+    (264, 256, 12, 2, 4),   # two chains, rows of 6 words
     (256, 256, 16, 8, 8),   # the 8-neighbourhood (statistic table of plain terms)
     (256, 256, 16, 16, 8),  # 8 neighbours, the largest statistic (8 * 15)
 ])

@@ -111,10 +111,10 @@ def test_random_batches_match_the_oracle(orc, seed):
 
 
 def _few_level_case(seed):
-    """A lattice with at most 16 levels large enough (at least 256 x 256) for one sweep per
+    """A lattice with at most 16 levels large enough (more than 256 x 256) for one sweep per
     launch, so the one-sweep few-level kernel runs rather than the several-sweeps one."""
     rng = np.random.default_rng(9700 + seed)
-    H, W = int(rng.integers(256, 321)), int(rng.integers(256, 321))
+    H, W = int(rng.integers(257, 321)), int(rng.integers(257, 321))
     L = int(rng.integers(2, 17))
     C = int(rng.choice([1, 2, 3, 4, 6, 8, 13, 16]))
     sweeps = int(rng.integers(1, 4 if C <= 8 else 3))
@@ -130,7 +130,7 @@ def _few_level_case(seed):
 
 @pytest.mark.parametrize("seed", range(12))
 def test_random_few_level_lattices_one_sweep_per_launch(orc, seed):
-    """Seeded random lattices of 256-320 sites a side with 2-16 levels and 1-16 chains (every
+    """Seeded random lattices of 257-320 sites a side with 2-16 levels and 1-16 chains (every
     lanes-per-pixel layout of the few-level kernel's statistics), either neighbourhood and
     prior: states, posterior means and marginal modes identical to the oracle's."""
     torch_cuda()
