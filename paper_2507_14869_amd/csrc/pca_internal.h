@@ -158,7 +158,7 @@ constexpr int kTbMaxSweeps = 16;
 constexpr int kTbBlock = 512;          // threads per workgroup (two waves per SIMD)
 constexpr int kTbItems = 2;            // items of the first sweep per thread, at most
 constexpr int kTbMaxLds = 64 * 1024;  // LDS bytes a workgroup may use
-constexpr int64_t kTbMaxThreads = 256 * 4 * 64;  // most single-sweep threads for which it is used
+constexpr int64_t kTbMaxThreads = 4 * 256 * 4 * 64;  // most single-sweep threads for which it is used
 
 struct TbArgs {
     SweepArgs a;      // a.t: first sweep; a.xin: state at a.t; a.xout: receives the state at

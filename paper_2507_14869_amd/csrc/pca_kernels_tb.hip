@@ -17,8 +17,9 @@
 // for a short dependent chain: every thread owns the same sites for the whole launch,
 // with their LDS addresses, neighbour presence and data factors (which depend on neither
 // the state nor beta) computed once; the level loop runs to a compile-time bound with no
-// branch; absent neighbours read a border of zeros; and the level sums and tallies of the
-// tile's sites stay in registers until the launch ends.
+// branch; absent neighbours read a border of zeros; with 8 or more levels the neighbour
+// statistics come from the statistic table of the one-sweep kernels; and the level sums and
+// tallies of the tile's sites stay in registers until the launch ends.
 #include <algorithm>
 
 #include "pca_sweep.h"
@@ -33,7 +34,7 @@ __host__ __device__ inline int tb_levels(int L) { return L <= 2 ? 2 : L <= 4 ? 4
 // LDS layout of one workgroup (byte offsets): the prior table and the two state buffers of
 // the loaded region, each with a border of zeros one site wide.
 struct TbLayout {
-    int ptab, xa, xb, bytes;
+    int ptab, vtab, xa, xb, bytes;
 };
 
 __host__ __device__ inline int tb_round16(int x) { return (x + 15) & ~15; }
@@ -44,7 +45,8 @@ __host__ __device__ inline TbLayout tb_lds_layout(int rh, int rw, int Cp, int pt
     TbLayout l;
     const int buf = tb_round16((rh + 2) * (rw + 2) * Cp);
     l.ptab = 0;
-    l.xa = tb_round16(ptab_n * 4);
+    l.vtab = tb_round16(ptab_n * 4);
+    l.xa = l.vtab + kStatEntries * 16;
     l.xb = l.xa + buf;
     l.bytes = l.xb + buf;
     return l;
@@ -134,19 +136,44 @@ __device__ __forceinline__ TbWords<NBR> tb_load(const TbItem<NW, LB> &it, const 
 // pix: the item's pixel (the counter of its random words).
 template <int G, int NBR, int LB>
 __device__ __forceinline__ uint32_t tb_draw(const TbItem<NBR / 4, LB> &it, const TbWords<NBR> &v, int pix,
-                                            const float *ptab, float R, float a2, uint32_t t, uint32_t key0,
-                                            uint32_t key1, int (&knew)[G])
+                                            const float *ptab, const uint4 *vtab, float R, float a2, uint32_t t,
+                                            uint32_t key0, uint32_t key1, int (&knew)[G])
 {
     constexpr int NW = NBR / 4;
+    // with 8 or more levels the statistics come from the statistic table (see
+    // fill_stat_table); byte k of a chain's sum is 4 S_k (4 neighbours) or S_k (8)
+    constexpr bool TSTAT = LB >= 8;
+    constexpr int kOffShift = NBR == 4 ? 0 : 2;
     const uint32_t own = v.own;
     const uint32_t(&nbw)[NBR] = v.nbw;
     float u[G];
     item_uniforms<G>(pix, it.grp, t, key0, key1, u);
 
+    uint32_t sv[G][4];
+    if constexpr (TSTAT) {
+#pragma unroll
+        for (int ch = 0; ch < G; ++ch)
+#pragma unroll
+            for (int d = 0; d < 4; ++d) sv[ch][d] = 0u;
+#pragma unroll
+        for (int j = 0; j < NBR; ++j) {
+            const bool present = ((it.tm[j / 4] >> (8 * (j % 4))) & 0xFFu) != 0u;
+            const uint32_t wj = present ? nbw[j] : 0x10101010u;  // absent: entry 16
+#pragma unroll
+            for (int ch = 0; ch < G; ++ch) {
+                const uint4 e = vtab[(wj >> (8 * ch)) & 0xFFu];
+                sv[ch][0] += e.x;
+                sv[ch][1] += e.y;
+                sv[ch][2] += e.z;
+                sv[ch][3] += e.w;
+            }
+        }
+    }
+
     // Neighbour packs of each chain (see NbrPack); absent neighbours are 0 with T = 0.
     NbrPack<NW> nb[G];
 #pragma unroll
-    for (int w = 0; w < NW; ++w) {
+    for (int w = 0; w < NW && !TSTAT; ++w) {
         uint32_t X[G];
         transpose_group<G>(nbw[4 * w], nbw[4 * w + 1], nbw[4 * w + 2], nbw[4 * w + 3], X);
 #pragma unroll
@@ -162,7 +189,7 @@ __device__ __forceinline__ uint32_t tb_draw(const TbItem<NBR / 4, LB> &it, const
         }
     }
 #pragma unroll
-    for (int ch = 0; ch < G; ++ch) nb[ch].cb *= 2;
+    for (int ch = 0; ch < G && !TSTAT; ++ch) nb[ch].cb *= 2;
 
     const char *pt = reinterpret_cast<const char *>(ptab);
     float P[LB][G];
@@ -170,7 +197,12 @@ __device__ __forceinline__ uint32_t tb_draw(const TbItem<NBR / 4, LB> &it, const
 #pragma unroll
     for (int k = 0; k < LB; ++k) {
 #pragma unroll
-        for (int ch = 0; ch < G; ++ch) P[k][ch] = prior_lookup<NW>(pt, nb[ch], kk);
+        for (int ch = 0; ch < G; ++ch) {
+            if constexpr (TSTAT)
+                P[k][ch] = *reinterpret_cast<const float *>(pt + (((sv[ch][k >> 2] >> (8 * (k & 3))) & 0xFFu) << kOffShift));
+            else
+                P[k][ch] = prior_lookup<NW>(pt, nb[ch], kk);
+        }
         kk += 0x01010101u;
     }
 
@@ -188,7 +220,15 @@ __device__ __forceinline__ uint32_t tb_draw(const TbItem<NBR / 4, LB> &it, const
         } else {
             const float ex = it.gp - (float)x;
             Dx = exp2s(__builtin_fmaf(-a2, ex * ex, it.m));
-            Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)x * 0x01010101u);
+            if constexpr (TSTAT) {
+                uint32_t s0 = sv[ch][0], s1 = sv[ch][1], s2 = sv[ch][2], s3 = sv[ch][3];
+                asm("" : "+v"(s0), "+v"(s1), "+v"(s2), "+v"(s3));
+                const uint32_t w01 = (x & 4) ? s1 : s0, w23 = (x & 4) ? s3 : s2;
+                const uint32_t w = (x & 8) ? w23 : w01;
+                Px = *reinterpret_cast<const float *>(pt + (((w >> (8 * (x & 3))) & 0xFFu) << kOffShift));
+            } else {
+                Px = prior_lookup<NW>(pt, nb[ch], (uint32_t)x * 0x01010101u);
+            }
         }
         const float stay = (Dx * Px) * R;
         float acc = stay;
@@ -262,6 +302,7 @@ __device__ __forceinline__ void tb_tile(SweepArgs a, int tile, int TS, int tiles
     const int h0 = gr1 - gr0, w0 = gc1 - gc0, wp = w0 + 2;
     const TbLayout lay = tb_lds_layout(h0, w0, Cp, ptab_n);
     float *ptab = reinterpret_cast<float *>(lds + lay.ptab);
+    uint4 *vtab = reinterpret_cast<uint4 *>(lds + lay.vtab);
     uint8_t *xa = lds + lay.xa;
     uint8_t *xb = lds + lay.xb;
 
@@ -352,6 +393,7 @@ __device__ __forceinline__ void tb_tile(SweepArgs a, int tile, int TS, int tiles
     // Sweep 0's prior table and constants.
     a.beta = sch.beta(0);
     fill_prior_table(a, NBR, ptab, tid, BLK);
+    if constexpr (LB >= 8) fill_stat_table(a, NBR, reinterpret_cast<uint32_t *>(vtab), tid, BLK);
     SweepConsts kc = sweep_constants(a);
     double beta_prev = a.beta;
 
@@ -424,7 +466,7 @@ __device__ __forceinline__ void tb_tile(SweepArgs a, int tile, int TS, int tiles
                 const TbWords<NBR> v = tb_load<G>(it[k], in, nofs);
                 int knew[G];
                 const uint32_t packed =
-                    tb_draw<G, NBR, LB>(it[k], v, it[k].pix, ptab, kc.R, kc.a2, t, a.key0, a.key1, knew);
+                    tb_draw<G, NBR, LB>(it[k], v, it[k].pix, ptab, vtab, kc.R, kc.a2, t, a.key0, a.key1, knew);
                 if (act) store_group<G>(out + it[k].off, packed);
                 if (k == 0 && it[0].own) tally_own(knew);
             }
@@ -656,15 +698,15 @@ TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia)
 {
     TbPlan pl{};
     if (L > 16 || inertia != 0) return pl;
-    // Only lattices whose single-sweep launch has at most as many threads as the GPU has
-    // lanes (256 CUs x 4 SIMDs x 64): there a sweep costs a launch and one site's latency,
-    // which several sweeps per launch amortise (256 x 256, one chain, 5 levels, 8 neighbours:
-    // 2.05 against 4.47 us per sweep; 4 chains, 16 levels: 5.16 against 5.73).  On larger
-    // ones the halo's extra work and the barriers cost about as much as they save or more
-    // (us per sweep, several against one sweep per launch: 256 x 256, 8 chains, 16 levels
-    // 6.99 / 6.78; 512 x 512, one chain, 9 levels, 8 neighbours 7.59 / 7.19; 512 x 512,
-    // 8 chains, 16 levels 23.7 / 19.3; but 384 x 384, one chain, 16 levels 5.05 / 5.99 and
-    // 512 x 512, one chain, 2 levels 3.44 / 5.40).
+    // Only lattices whose single-sweep launch has at most four threads per lane of the GPU
+    // (256 CUs x 4 SIMDs x 64, four waves per SIMD): there a sweep costs a launch and little
+    // more than one site's latency, which several sweeps per launch amortise.  Measured (us
+    // per sweep, several against one sweep per launch, results identical): 256 x 256, one
+    // chain, 5 levels, 8 neighbours 1.97 / 4.47; 384 x 384, one chain, 16 levels 4.44 / 5.90;
+    // 256 x 256, 8 chains, 16 levels 5.88 / 6.66; 512 x 512, one chain, 9 levels, 8 neighbours
+    // 6.35 / 7.15, 16 levels 5.71 / 7.46, 2 levels 3.44 / 5.40.  Beyond that the halo's extra
+    // work and the barriers cost more than they save (512 x 512, 8 chains, 16 levels: 27.9
+    // against 19.4 before the statistic table, which both kernels now use).
     const int G = chain_group(Cp);
     if ((int64_t)H * W * (Cp / G) > kTbMaxThreads) return pl;
     // Tiles as large as keep every compute unit busy (about one workgroup each), down to

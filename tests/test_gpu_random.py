@@ -111,13 +111,16 @@ def test_random_batches_match_the_oracle(orc, seed):
 
 
 def _few_level_case(seed):
-    """A lattice with at most 16 levels large enough (more than 256 x 256) for one sweep per
-    launch, so the one-sweep few-level kernel runs rather than the several-sweeps one."""
+    """A lattice with at most 16 levels large enough (more than four single-sweep threads per
+    lane of the GPU) for one sweep per launch, so the one-sweep few-level kernel runs rather
+    than the several-sweeps one."""
     rng = np.random.default_rng(9700 + seed)
-    H, W = int(rng.integers(257, 321)), int(rng.integers(257, 321))
     L = int(rng.integers(2, 17))
     C = int(rng.choice([1, 2, 3, 4, 6, 8, 13, 16]))
-    sweeps = int(rng.integers(1, 4 if C <= 8 else 3))
+    tpp = 1 if C <= 4 else (C + 3) // 4  # threads per pixel (chain groups of up to 4)
+    side = int(np.ceil(np.sqrt(4 * 256 * 4 * 64 / tpp))) + 1  # above the several-sweeps limit
+    H, W = int(rng.integers(side, side + 64)), int(rng.integers(side, side + 64))
+    sweeps = int(rng.integers(1, 3))
     truth = synth.random_image(H, W, L, int(rng.integers(5, 40)), L > 2, rng)
     obs = synth.noisy_observation(truth, L, 0.0, float(L - 1), float(rng.uniform(0.1, 0.3)) * L, rng)
     kw = dict(height=H, width=W, levels=L, chains=C, neighbourhood=int(rng.choice([4, 8])),
@@ -130,7 +133,7 @@ def _few_level_case(seed):
 
 @pytest.mark.parametrize("seed", range(12))
 def test_random_few_level_lattices_one_sweep_per_launch(orc, seed):
-    """Seeded random lattices of 257-320 sites a side with 2-16 levels and 1-16 chains (every
+    """Seeded random lattices of 257-576 sites a side with 2-16 levels and 1-16 chains (every
     lanes-per-pixel layout of the few-level kernel's statistics), either neighbourhood and
     prior: states, posterior means and marginal modes identical to the oracle's."""
     torch_cuda()
