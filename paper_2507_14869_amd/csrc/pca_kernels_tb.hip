@@ -705,8 +705,8 @@ TbPlan tb_plan(int H, int W, int L, int Cp, int nbr, int T, int inertia)
     // chain, 5 levels, 8 neighbours 1.97 / 4.47; 384 x 384, one chain, 16 levels 4.44 / 5.90;
     // 256 x 256, 8 chains, 16 levels 5.88 / 6.66; 512 x 512, one chain, 9 levels, 8 neighbours
     // 6.35 / 7.15, 16 levels 5.71 / 7.46, 2 levels 3.44 / 5.40.  Beyond that the halo's extra
-    // work and the barriers cost more than they save (512 x 512, 8 chains, 16 levels: 27.9
-    // against 19.4 before the statistic table, which both kernels now use).
+    // work and the barriers cost more than they save (512 x 512, 8 chains, 16 levels: 22.2
+    // against 16.1).
     const int G = chain_group(Cp);
     if ((int64_t)H * W * (Cp / G) > kTbMaxThreads) return pl;
     // Tiles as large as keep every compute unit busy (about one workgroup each), down to
