@@ -54,10 +54,10 @@ def valu_ops_per_site_update(levels: int, chains: int, inertia: int = 0, nbr: in
 
 def peak_note(wl, inertia: int, sweeps_per_launch: int) -> str:
     """What the VALU peak is and how the kernel's instruction mix relates to the ops model
-    (the several-sweeps kernel of small lattices keeps the byte SADs)."""
+    (the several-sweeps kernel keeps the byte SADs for at most 4 levels)."""
     base = ("32-bit VALU issue rate, 256 CUs x 128 lanes x 2.4 GHz (the FP32 vector peak counts an fma as "
             "two flops); ")
-    if wl.levels <= 16 and inertia == 0 and sweeps_per_launch == 1:
+    if wl.levels <= 16 and inertia == 0 and (sweeps_per_launch == 1 or wl.levels > 4):
         return base + ("with at most 16 levels the kernel takes each (chain, level)'s neighbour statistic "
                        "from an LDS byte table (one byte extract and one fma per (chain, level) instead of "
                        "three byte SADs per four neighbours, a shift-add and a 24-bit mad), so the dense-"
